@@ -1,0 +1,156 @@
+"""Benchmark: site updates/s of the coupled-pair Metropolis sweep on the large
+single lattice (L = 8192, 67M sites, 2-bit states) on one MI355X.
+
+One step = one observation interval of the workload: 50 sweeps (4 phase
+launches each) followed by the grid-wide observable reduction.  The lattice is
+created (init, threshold table) before the timed region, so its inputs are
+resident in HBM when timing starts.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 full-rate 32-bit
+# integer VALU lane-operations per second.
+VALU_PEAK_OPS = 256 * 64 * 2.4e9
+HBM_PEAK_GBS = 8000.0
+# Algorithmic integer work per site update that the method fixes: half a
+# Philox4x32-10 call per pair, i.e. a quarter call per site update; a call is
+# 10 rounds of two 32x32->64 multiplies (quarter rate: 4 slots each) and two
+# three-input xors (1 slot each) = 100 full-rate slots.
+ALU_OPS_PER_SITE_UPDATE = 25.0
+# Algorithmic HBM bytes per site update at 2 bits per site: read + write once.
+BYTES_PER_SITE_UPDATE_2BIT = 0.5
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    return ap.parse_args()
+
+
+def cpu_baseline(spec: workloads.LatticeSpec, sweeps: int) -> dict:
+    """The oracle (single thread) on the same lattice: init untimed, then
+    `sweeps` sweeps timed."""
+    import oracle
+
+    o = oracle.OracleLattice(spec.L, spec.n, spec.Delta, spec.V, spec.J, spec.T, spec.seed)
+    t0 = time.perf_counter()
+    o.sweeps(sweeps)
+    dt = time.perf_counter() - t0
+    return {
+        "value": spec.L * spec.L * sweeps / dt,
+        "unit": "site updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{sweeps} sweeps of the L={spec.L} lattice (same parameters and seed), init not timed",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2301_11735_amd as lat
+
+    spec = workloads.LARGE
+    every = spec.every
+    N = spec.L * spec.L
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    g = lat.Lattice(spec.L, spec.n, spec.Delta, spec.V, spec.J, spec.T, spec.seed, encoding=spec.encoding,
+                    stream=stream)
+    o0 = g.observables()
+
+    for _ in range(args.warmup):
+        g.sweep(every)
+        g.observables()
+    torch.cuda.synchronize()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    obs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1, e2 in ev:
+        e0.record(stream)
+        g.sweep(every)
+        e1.record(stream)
+        obs.append(g.observables())  # synchronises the stream
+        e2.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    sweep_ms = sum(e0.elapsed_time(e1) for e0, e1, _ in ev)
+    phase_us = sweep_ms * 1e3 / (args.steps * every * 4)
+    value = N * every * args.steps / wall
+    per_launch_updates = N / 4  # one phase updates N/8 pairs
+    alu_achieved = per_launch_updates * ALU_OPS_PER_SITE_UPDATE / (phase_us * 1e-6)
+
+    last = obs[-1]
+    Q, _ = lat.charge_target(spec.L, spec.n)
+    assert last.sum_S == Q, "charge constraint violated"
+    assert last.track_nD == last.n_charged - o0.n_charged, "tracker drifted from the recomputed energy"
+
+    line = {
+        "metric": "site updates/sec at L=8192",
+        "value": value,
+        "unit": "site updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "large single lattice L=8192 (67M sites), 2-bit states, J=1 V=0.5 Delta=0.25 T=1.2 "
+                        "n=0.1 seed 3, step = 50 sweeps + observable reduction",
+            "L": spec.L,
+            "sweeps_per_step": every,
+            "encoding": "2bit",
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": alu_achieved / 1e12,
+            "peak": VALU_PEAK_OPS / 1e12,
+            "unit": "Tops/s",
+            "frac": alu_achieved / VALU_PEAK_OPS,
+            "traffic": None,
+            "kernel": "k_phase_2bit",
+            "avg_launch_us": phase_us,
+        },
+        "hbm_effective": {
+            "GB_per_s": value * BYTES_PER_SITE_UPDATE_2BIT / 1e9,
+            "frac_of_peak": value * BYTES_PER_SITE_UPDATE_2BIT / 1e9 / HBM_PEAK_GBS,
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(spec, args.cpu_sweeps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,143 @@
+/*
+ * lattice.h -- C-ABI of liblattice.so: the coupled-pair Metropolis sweep with an
+ * exact charge constraint on an L x L periodic lattice of four-state sites,
+ * on one MI355X (gfx950).
+ *
+ * Method: Budrin, Ulitko, Chikov, Panov, Moskvin, arXiv:2301.11735.
+ *   Model and energy: section 2.1, eq. (1) and the sigma form eq. (3)
+ *     E = Delta sum S_i^2 + V sum_<ij> S_i S_j + (J/4) sum_<ij> sigma_i sigma_j.
+ *   Constraint: eq. (2), sum S_i = nN, held exactly at every step.
+ *   Update: section 3.1 ("Algorithm"): a coupled pair keeps its charge and
+ *     takes a random configuration of the same-charge set, accepted by the
+ *     classical Metropolis rule.
+ *   Parallel form: section 3.2: only pairs that do not interact are updated
+ *     together; partners are long-range random.
+ *
+ * Site codes (one per site in the canonical layout, row-major, site (x,y) at
+ * index y*L + x): 0 = spin up (S=0, sigma=+1), 1 = spin down (S=0, sigma=-1),
+ * 2 = charge S=+1, 3 = charge S=-1.
+ *
+ * Conventions for every call:
+ *   - Device pointers are HIP device memory (e.g. from torch.empty on a ROCm
+ *     device); host pointers are ordinary host memory.  The caller owns all
+ *     memory; the library never allocates or frees device memory.
+ *   - Return value 0 on success, or a negative LAT_E* code.  The text of the
+ *     last error of the calling thread is returned by lattice_last_error().
+ *   - A handle is not thread-safe; all of its work is ordered on the stream
+ *     given at creation.  Calls that return data to the host synchronise
+ *     that stream.
+ */
+#ifndef PAPER_2301_11735_LATTICE_H
+#define PAPER_2301_11735_LATTICE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LAT_OK 0
+#define LAT_EINVAL (-1) /* invalid argument (geometry, parameters, codes, null pointer) */
+#define LAT_ENOMEM (-2) /* a caller buffer is smaller than required */
+#define LAT_EHIP (-3)   /* a HIP runtime call failed; see lattice_last_error() */
+#define LAT_ESTATE (-4) /* misuse: null or destroyed handle */
+
+/* State encodings of the device buffer.
+ *   LAT_ENC_INT8: one code per byte, canonical row-major layout; L % 4 == 0.
+ *   LAT_ENC_2BIT: 2 bits per site, N/4 bytes; L % 64 == 0.  Sites are stored
+ *     by sublattice class: class c = 4*(y mod 2) + (x mod 4) holds the
+ *     (L/4) x (L/2) sites x = 4X + (x mod 4), y = 2Y + (y mod 2); class c
+ *     starts at 32-bit word c*(L/2)*(L/64); class row Y is L/64 words; site X
+ *     of the row is bits 2*(X mod 16) of word X/16 (little-endian). */
+#define LAT_ENC_INT8 0
+#define LAT_ENC_2BIT 1
+
+typedef struct lattice lattice; /* opaque host-side handle */
+
+typedef struct {
+    int32_t L;            /* side; >= 4 and L % 4 == 0 (int8) or L % 64 == 0 (2-bit) */
+    int32_t encoding;     /* LAT_ENC_INT8 or LAT_ENC_2BIT */
+    double n;             /* target charge density of eq. (2); |n| <= 1 */
+    double Delta, V, J;   /* couplings of eq. (3); finite */
+    double T;             /* temperature (k = 1); finite and > 0 */
+    uint64_t seed;        /* Philox4x32-10 key */
+    int64_t n_charged;    /* number of charged sites at init; -1 = max(N/4, |Q|) */
+    uint64_t start_sweep; /* index of the first sweep (0, or a resume point) */
+    const int8_t *init_codes; /* NULL: seeded init; else N host codes (row-major)
+                                 used verbatim, and Q, Nc are taken from them */
+} lat_params;
+
+typedef struct {
+    uint64_t sweep;      /* sweeps done so far, counted from start_sweep */
+    int64_t sum_S;       /* sum S_i (eq. 2; constant) */
+    int64_t n_charged;   /* sum S_i^2 */
+    int64_t bond_SS;     /* sum over the 2N bonds of S_i S_j */
+    int64_t bond_ss;     /* sum over the 2N bonds of sigma_i sigma_j */
+    int64_t M;           /* sum sigma_i */
+    int64_t M_stag;      /* sum (-1)^(x+y) sigma_i */
+    int64_t C_stag;      /* sum (-1)^(x+y) S_i */
+    int64_t track_nD;    /* sum over accepted moves of the change of n_charged */
+    int64_t track_nV;    /* ... of bond_SS */
+    int64_t track_nJ;    /* ... of bond_ss */
+    double E;            /* Delta*n_charged + V*bond_SS + 0.25*J*bond_ss (FP64) */
+} lat_obs;
+
+/* Bytes of the device state buffer for side L: N (int8) or N/4 (2-bit).
+ * Returns 0 if L is not valid for the encoding. */
+size_t lattice_state_bytes(int32_t L, int32_t encoding);
+
+/* Bytes of the device scratch buffer a lattice needs (threshold table,
+ * energy tracker, reduction slots).  Independent of L. */
+size_t lattice_scratch_bytes(int32_t L, int32_t encoding);
+
+/* Charge target of eq. (2) for side L and density n (Q rounded to the
+ * parity of the charged count; n_charged = -1 picks max(N/4, |Q|)).
+ * Writes Q and the charged count; LAT_EINVAL if none exists. */
+int lattice_charge_target(int32_t L, double n, int64_t n_charged, int64_t *Q, int64_t *Nc);
+
+/* Create a lattice: validate p, compute the charge target (eq. 2), build the
+ * initial configuration (stage 1 of section 3.1) and the Metropolis threshold
+ * table (section 3.1, eq. 3), and copy both to the caller's device buffers on
+ * hip_stream (a hipStream_t, or NULL for the default stream).  d_state must
+ * hold lattice_state_bytes(), d_scratch lattice_scratch_bytes(); both must
+ * stay valid until lattice_destroy.  The copies are asynchronous; host
+ * memory of p->init_codes may be reused once the call returns.
+ * Errors: LAT_EINVAL (bad geometry, |Q| > Nc, Nc > N, n_charged of the wrong
+ * parity, non-finite parameters, T <= 0, codes outside 0..3, null pointers),
+ * LAT_ENOMEM (a buffer too small), LAT_EHIP. */
+int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void *d_scratch,
+                   size_t scratch_bytes, void *hip_stream, lattice **out);
+
+/* Advance by `sweeps` sweeps (section 3.1 update, section 3.2 parallel form):
+ * each sweep is four phases of N/8 non-interacting coupled pairs, so every
+ * site is updated once per sweep.  Asynchronous on the handle's stream.
+ * Errors: LAT_ESTATE, LAT_EHIP. */
+int lattice_sweep(lattice *h, uint32_t sweeps);
+
+/* Reduce the current configuration to its integer observables, read the
+ * incremental energy tracker, and fill *out (E in FP64 on the host).
+ * Synchronises the handle's stream.  Errors: LAT_ESTATE, LAT_EINVAL, LAT_EHIP. */
+int lattice_observables(lattice *h, lat_obs *out);
+
+/* Copy the configuration to N host codes in the canonical row-major layout.
+ * Synchronises the handle's stream.  Errors: LAT_ESTATE, LAT_EINVAL, LAT_EHIP. */
+int lattice_read_state(lattice *h, int8_t *host_codes);
+
+/* Advance `count` lattices by `sweeps` sweeps each, on hip_stream (section
+ * 3.2: several lattice copies processed together).  Lattices may differ in
+ * L, parameters and seed; results are identical to calling lattice_sweep on
+ * each.  Errors: LAT_EINVAL, LAT_ESTATE, LAT_EHIP. */
+int lattice_sweep_batch(lattice *const *hs, int32_t count, uint32_t sweeps, void *hip_stream);
+
+/* Release the handle (host memory only; caller buffers are untouched). */
+int lattice_destroy(lattice *h);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char *lattice_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPER_2301_11735_LATTICE_H */

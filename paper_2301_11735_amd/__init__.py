@@ -1,0 +1,212 @@
+"""Python binding of liblattice.so (include/lattice.h): the coupled-pair
+Metropolis sweep with an exact charge constraint (arXiv:2301.11735) on MI355X.
+
+Argument marshalling only.  Every step of a sweep runs in the library's HIP
+kernels; PyTorch supplies the device buffers and the stream.  There is no CPU
+fallback: without the built library, or without a GPU, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblattice.so")
+
+LAT_OK, LAT_EINVAL, LAT_ENOMEM, LAT_EHIP, LAT_ESTATE = 0, -1, -2, -3, -4
+ENC_INT8, ENC_2BIT = 0, 1
+
+EXPORTS = (
+    "lattice_state_bytes",
+    "lattice_scratch_bytes",
+    "lattice_charge_target",
+    "lattice_create",
+    "lattice_sweep",
+    "lattice_observables",
+    "lattice_read_state",
+    "lattice_sweep_batch",
+    "lattice_destroy",
+    "lattice_last_error",
+)
+
+
+class LatParams(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32),
+        ("encoding", ctypes.c_int32),
+        ("n", ctypes.c_double),
+        ("Delta", ctypes.c_double),
+        ("V", ctypes.c_double),
+        ("J", ctypes.c_double),
+        ("T", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("n_charged", ctypes.c_int64),
+        ("start_sweep", ctypes.c_uint64),
+        ("init_codes", ctypes.POINTER(ctypes.c_int8)),
+    ]
+
+
+class LatObs(ctypes.Structure):
+    _fields_ = [
+        ("sweep", ctypes.c_uint64),
+        ("sum_S", ctypes.c_int64),
+        ("n_charged", ctypes.c_int64),
+        ("bond_SS", ctypes.c_int64),
+        ("bond_ss", ctypes.c_int64),
+        ("M", ctypes.c_int64),
+        ("M_stag", ctypes.c_int64),
+        ("C_stag", ctypes.c_int64),
+        ("track_nD", ctypes.c_int64),
+        ("track_nV", ctypes.c_int64),
+        ("track_nJ", ctypes.c_int64),
+        ("E", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+    def ints(self) -> list:
+        """(sum_S, n_charged, bond_SS, bond_ss, M, M_stag, C_stag) in the oracle's order."""
+        return [self.sum_S, self.n_charged, self.bond_SS, self.bond_ss, self.M, self.M_stag, self.C_stag]
+
+
+class LatticeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"liblattice error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load liblattice.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2301_11735_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        L.lattice_state_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.lattice_state_bytes.restype = sz
+        L.lattice_scratch_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.lattice_scratch_bytes.restype = sz
+        L.lattice_charge_target.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_int64,
+                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.lattice_charge_target.restype = ctypes.c_int
+        L.lattice_create.argtypes = [ctypes.POINTER(LatParams), vp, sz, vp, sz, vp, ctypes.POINTER(vp)]
+        L.lattice_create.restype = ctypes.c_int
+        L.lattice_sweep.argtypes = [vp, ctypes.c_uint32]
+        L.lattice_sweep.restype = ctypes.c_int
+        L.lattice_observables.argtypes = [vp, ctypes.POINTER(LatObs)]
+        L.lattice_observables.restype = ctypes.c_int
+        L.lattice_read_state.argtypes = [vp, ctypes.POINTER(ctypes.c_int8)]
+        L.lattice_read_state.restype = ctypes.c_int
+        L.lattice_sweep_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_uint32, vp]
+        L.lattice_sweep_batch.restype = ctypes.c_int
+        L.lattice_destroy.argtypes = [vp]
+        L.lattice_destroy.restype = ctypes.c_int
+        L.lattice_last_error.argtypes = []
+        L.lattice_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != LAT_OK:
+        raise LatticeError(rc, lib().lattice_last_error().decode())
+
+
+def state_bytes(L: int, encoding: int) -> int:
+    return int(lib().lattice_state_bytes(L, encoding))
+
+
+def scratch_bytes(L: int, encoding: int) -> int:
+    return int(lib().lattice_scratch_bytes(L, encoding))
+
+
+def charge_target(L: int, n: float, n_charged: int = -1):
+    Q, Nc = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().lattice_charge_target(L, n, n_charged, ctypes.byref(Q), ctypes.byref(Nc)))
+    return Q.value, Nc.value
+
+
+def _stream_handle(stream) -> int:
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Lattice:
+    """One lattice on the GPU.  Buffers are torch uint8 tensors owned here;
+    the library borrows them until destroy()."""
+
+    def __init__(self, L: int, n: float, Delta: float, V: float, J: float, T: float, seed: int,
+                 encoding: int = ENC_INT8, n_charged: int = -1, start_sweep: int = 0, init_codes=None,
+                 device: str = "cuda", stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("a ROCm GPU is required (torch.cuda.is_available() is False)")
+        self.L, self.encoding = L, encoding
+        self.params = dict(L=L, n=n, Delta=Delta, V=V, J=J, T=T, seed=seed, encoding=encoding,
+                           n_charged=n_charged, start_sweep=start_sweep)
+        sb = state_bytes(L, encoding)
+        if sb == 0:
+            raise ValueError(f"L={L} is not valid for encoding {encoding}")
+        self.state = torch.empty(sb, dtype=torch.uint8, device=device)
+        self.scratch = torch.empty(scratch_bytes(L, encoding), dtype=torch.uint8, device=device)
+        self.stream = stream
+        p = LatParams(L=L, encoding=encoding, n=n, Delta=Delta, V=V, J=J, T=T, seed=seed, n_charged=n_charged,
+                      start_sweep=start_sweep, init_codes=None)
+        self._init = None
+        if init_codes is not None:
+            self._init = np.ascontiguousarray(init_codes, dtype=np.int8).reshape(-1)
+            if self._init.size != L * L:
+                raise ValueError("init_codes must hold L*L codes")
+            p.init_codes = self._init.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+        h = ctypes.c_void_p()
+        _check(lib().lattice_create(ctypes.byref(p), self.state.data_ptr(), self.state.numel(),
+                                    self.scratch.data_ptr(), self.scratch.numel(), _stream_handle(stream),
+                                    ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise LatticeError(LAT_ESTATE, "lattice destroyed")
+        return self._h
+
+    def sweep(self, sweeps: int = 1):
+        _check(lib().lattice_sweep(self.handle, sweeps))
+
+    def observables(self) -> LatObs:
+        o = LatObs()
+        _check(lib().lattice_observables(self.handle, ctypes.byref(o)))
+        return o
+
+    def read_state(self) -> np.ndarray:
+        out = np.empty(self.L * self.L, dtype=np.int8)
+        _check(lib().lattice_read_state(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))))
+        return out
+
+    def destroy(self):
+        if self._h is not None:
+            _check(lib().lattice_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def sweep_batch(lattices, sweeps: int, stream=None):
+    """Advance several lattices by `sweeps` sweeps each in one call."""
+    arr = (ctypes.c_void_p * len(lattices))(*[lat.handle.value for lat in lattices])
+    _check(lib().lattice_sweep_batch(arr, len(lattices), sweeps, _stream_handle(stream)))

@@ -1,0 +1,394 @@
+// Host side of liblattice.so: the C-ABI of include/lattice.h.
+//
+// Parameter checks and the charge target (eq. 2), the stage-1 initial
+// configuration (section 3.1), the FP64 Metropolis threshold table (section
+// 3.1, eq. 3), the per-sweep schedule of non-interacting pairs (section 3.2)
+// and the layout conversion between canonical codes and the device encodings.
+// All sweep and reduction work runs in the kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/lattice.h"
+#include "kernels.h"
+#include "philox.h"
+
+using namespace lat;
+
+struct lattice {
+    int L = 0, enc = 0;
+    int64_t N = 0, Q = 0, Nc = 0;
+    double n = 0, Delta = 0, V = 0, J = 0, T = 1;
+    uint64_t seed = 0, start_sweep = 0, done = 0;
+    void *d_state = nullptr;
+    uint8_t *d_scratch = nullptr;
+    hipStream_t stream = nullptr;
+    uint32_t magic = 0;
+};
+
+namespace {
+
+constexpr uint32_t kMagic = 0x1A771CEu;
+constexpr int kMaxL = 32768;
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(LAT_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool valid_geometry(int32_t L, int32_t enc)
+{
+    if (L < 4 || L > kMaxL) return false;
+    if (enc == LAT_ENC_INT8) return L % 4 == 0;
+    if (enc == LAT_ENC_2BIT) return L % 64 == 0;
+    return false;
+}
+
+// Eq. (2) made an integer: Q nearest nN with the parity of the charged count
+// (ties to the smaller); without a requested count, Nc = max(N/4, |Q|).
+int charge_target(int32_t L, double n, int64_t n_req, int64_t *Q_out, int64_t *Nc_out)
+{
+    const int64_t N = (int64_t)L * L;
+    const double target = n * (double)N;
+    if (!std::isfinite(target) || std::fabs(target) > (double)N) return fail(LAT_EINVAL, "n must satisfy |n| <= 1");
+    const int64_t nc0 = n_req >= 0 ? n_req : N / 4;
+    if (nc0 > N) return fail(LAT_EINVAL, "n_charged exceeds N");
+    const int64_t parity = nc0 & 1;
+    int64_t lo = (int64_t)std::floor(target);
+    if ((lo & 1) != parity) lo -= 1;  // two's complement: & 1 is the parity for negatives too
+    const int64_t hi = lo + 2;
+    const int64_t Q = ((double)hi - target < target - (double)lo) ? hi : lo;
+    int64_t Nc = nc0;
+    if (std::llabs(Q) > nc0) {
+        if (n_req >= 0) return fail(LAT_EINVAL, "|Q| exceeds the requested number of charged sites");
+        Nc = std::llabs(Q);
+    }
+    if (Nc > N) return fail(LAT_EINVAL, "no charge target fits the lattice");
+    *Q_out = Q;
+    *Nc_out = Nc;
+    return LAT_OK;
+}
+
+// Stage 1 of section 3.1: site i gets key (w0 << 32 | w1) of Philox counter
+// (0, 0x200, i, 0); the N+ smallest (key, i) become +1, the next N- become -1,
+// the others are spins with sigma from bit 0 of w2.  Selection (two
+// nth_element passes) gives the same sets as a full sort.
+void seeded_init(int32_t L, uint64_t seed, int64_t n_plus, int64_t n_minus, std::vector<int8_t> &codes)
+{
+    const int64_t N = (int64_t)L * L;
+    struct Key {
+        uint64_t k;
+        uint32_t i;
+        bool operator<(const Key &o) const { return k != o.k ? k < o.k : i < o.i; }
+    };
+    std::vector<Key> keys((size_t)N);
+    codes.assign((size_t)N, 0);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (N < (1 << 16)) nt = 1;
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < nt; ++t) {
+        pool.emplace_back([&, t] {
+            const int64_t b = N * t / nt, e = N * (t + 1) / nt;
+            for (int64_t i = b; i < e; ++i) {
+                const u32x4 w = philox4x32_10(0u, kDomInit, (uint32_t)i, 0u, k0, k1);
+                keys[(size_t)i] = Key{((uint64_t)w.x << 32) | w.y, (uint32_t)i};
+                codes[(size_t)i] = (int8_t)(w.z & 1u);
+            }
+        });
+    }
+    for (auto &th : pool) th.join();
+    const int64_t nc = n_plus + n_minus;
+    if (nc > 0) {
+        if (nc < N) std::nth_element(keys.begin(), keys.begin() + nc, keys.end());
+        if (n_plus > 0 && n_plus < nc) std::nth_element(keys.begin(), keys.begin() + n_plus, keys.begin() + nc);
+        for (int64_t r = 0; r < nc; ++r) codes[keys[(size_t)r].i] = (int8_t)(r < n_plus ? 2 : 3);
+    }
+}
+
+// Section 3.1: classical Metropolis acceptance for every energy-change triple,
+// dE = Delta*nD + V*nV + 0.25*J*nJ (eq. 3) in FP64; "always" for dE <= 0.
+void build_threshold_table(double Delta, double V, double J, double T, std::vector<uint32_t> &tab)
+{
+    tab.assign(kTabSize, 0u);
+    for (int nD = -2; nD <= 2; ++nD)
+        for (int nV = -16; nV <= 16; ++nV)
+            for (int nJ = -16; nJ <= 16; ++nJ) {
+                const double dE = Delta * nD + V * nV + 0.25 * J * nJ;
+                uint32_t t;
+                if (dE <= 0.0) {
+                    t = 0xFFFFFFFFu;
+                } else {
+                    const double f = std::floor(std::exp(-dE / T) * 4294967296.0);
+                    t = f >= 4294967294.0 ? 0xFFFFFFFEu : (uint32_t)f;
+                }
+                tab[(size_t)(nD + 2) * (kTabV * kTabJ) + (size_t)(nV + 16) * kTabJ + (size_t)(nJ + 16)] = t;
+            }
+}
+
+// Canonical row-major codes <-> device encoding.
+void to_device_layout(int32_t L, int32_t enc, const std::vector<int8_t> &codes, std::vector<uint8_t> &out)
+{
+    const size_t N = (size_t)L * L;
+    if (enc == LAT_ENC_INT8) {
+        out.assign((const uint8_t *)codes.data(), (const uint8_t *)codes.data() + N);
+        return;
+    }
+    const size_t W = (size_t)L / 64, H = (size_t)L / 2, csz = H * W;
+    std::vector<uint32_t> words(N / 16, 0u);
+    for (size_t y = 0; y < (size_t)L; ++y)
+        for (size_t x = 0; x < (size_t)L; ++x) {
+            const size_t c = 4 * (y & 1) + (x & 3), X = x >> 2, Y = y >> 1;
+            words[c * csz + Y * W + (X >> 4)] |= (uint32_t)(codes[y * L + x] & 3) << (2 * (X & 15));
+        }
+    out.resize(N / 4);
+    std::memcpy(out.data(), words.data(), N / 4);
+}
+
+void from_device_layout(int32_t L, int32_t enc, const std::vector<uint8_t> &dev, int8_t *codes)
+{
+    const size_t N = (size_t)L * L;
+    if (enc == LAT_ENC_INT8) {
+        std::memcpy(codes, dev.data(), N);
+        return;
+    }
+    const size_t W = (size_t)L / 64, H = (size_t)L / 2, csz = H * W;
+    const uint32_t *words = (const uint32_t *)dev.data();
+    for (size_t y = 0; y < (size_t)L; ++y)
+        for (size_t x = 0; x < (size_t)L; ++x) {
+            const size_t c = 4 * (y & 1) + (x & 3), X = x >> 2, Y = y >> 1;
+            codes[y * L + x] = (int8_t)((words[c * csz + Y * W + (X >> 4)] >> (2 * (X & 15))) & 3u);
+        }
+}
+
+// Schedule of sweep s (section 3.2: non-interacting pairs, long-range
+// partners): r in {1,2,3}; phase p has D_p = (r + 4 m_p, 1 + 2 k_p).
+struct Schedule {
+    int r, m[4], k[4];
+};
+
+Schedule sweep_schedule(int32_t L, uint64_t seed, uint64_t s)
+{
+    uint32_t Wd[12];
+    for (uint32_t t = 0; t < 3; ++t) {
+        const u32x4 w = philox4x32_10((uint32_t)s, kDomSchedule, t, (uint32_t)(s >> 32), (uint32_t)seed,
+                                      (uint32_t)(seed >> 32));
+        Wd[4 * t] = w.x;
+        Wd[4 * t + 1] = w.y;
+        Wd[4 * t + 2] = w.z;
+        Wd[4 * t + 3] = w.w;
+    }
+    Schedule sc;
+    sc.r = 1 + (int)(((uint64_t)(Wd[0] >> 8) * 3u) >> 24);
+    for (int p = 0; p < 4; ++p) {
+        sc.m[p] = (int)mulhi_u32(Wd[1 + 2 * p], (uint32_t)(L / 4));
+        sc.k[p] = (int)mulhi_u32(Wd[2 + 2 * p], (uint32_t)(L / 2));
+    }
+    return sc;
+}
+
+bool live(const lattice *h) { return h != nullptr && h->magic == kMagic; }
+
+int enqueue_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
+{
+    PhaseArgs a{};
+    a.state = h->d_state;
+    a.thr = (const uint32_t *)(h->d_scratch + kScrTable);
+    a.track = (unsigned long long *)(h->d_scratch + kScrTrack);
+    a.L = h->L;
+    a.key0 = (uint32_t)h->seed;
+    a.key1 = (uint32_t)(h->seed >> 32);
+    for (uint32_t i = 0; i < sweeps; ++i) {
+        const uint64_t s = h->start_sweep + h->done + i;
+        const Schedule sc = sweep_schedule(h->L, h->seed, s);
+        a.s_lo = (uint32_t)s;
+        a.s_hi = (uint32_t)(s >> 32);
+        a.r = sc.r;
+        for (int p = 0; p < 4; ++p) {
+            a.p = p;
+            a.m = sc.m[p];
+            a.k = sc.k[p];
+            const hipError_t e =
+                h->enc == LAT_ENC_INT8 ? launch_phase_int8(a, stream) : launch_phase_2bit(a, stream);
+            if (e != hipSuccess) return hip_fail(e, "phase kernel launch");
+        }
+    }
+    h->done += sweeps;
+    return LAT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lattice_state_bytes(int32_t L, int32_t encoding)
+{
+    if (!valid_geometry(L, encoding)) return 0;
+    const size_t N = (size_t)L * L;
+    return encoding == LAT_ENC_INT8 ? N : N / 4;
+}
+
+size_t lattice_scratch_bytes(int32_t L, int32_t encoding)
+{
+    (void)L;
+    (void)encoding;
+    return kScrBytes;
+}
+
+int lattice_charge_target(int32_t L, double n, int64_t n_charged, int64_t *Q, int64_t *Nc)
+{
+    if (!Q || !Nc) return fail(LAT_EINVAL, "null output pointer");
+    if (L < 1 || L > kMaxL) return fail(LAT_EINVAL, "L out of range");
+    return charge_target(L, n, n_charged, Q, Nc);
+}
+
+int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void *d_scratch, size_t scratch_bytes,
+                   void *hip_stream, lattice **out)
+{
+    g_err.clear();
+    if (!p || !out) return fail(LAT_EINVAL, "null params or output handle");
+    *out = nullptr;
+    if (!valid_geometry(p->L, p->encoding))
+        return fail(LAT_EINVAL, "invalid L for the encoding (int8: L%4==0; 2-bit: L%64==0; 4 <= L <= 32768)");
+    if (!std::isfinite(p->Delta) || !std::isfinite(p->V) || !std::isfinite(p->J) || !std::isfinite(p->T) ||
+        !std::isfinite(p->n))
+        return fail(LAT_EINVAL, "parameters must be finite");
+    if (!(p->T > 0.0)) return fail(LAT_EINVAL, "T must be > 0");
+    if (!d_state || !d_scratch) return fail(LAT_EINVAL, "null device buffer");
+    if (state_bytes < lattice_state_bytes(p->L, p->encoding)) return fail(LAT_ENOMEM, "state buffer too small");
+    if (scratch_bytes < kScrBytes) return fail(LAT_ENOMEM, "scratch buffer too small");
+
+    const int64_t N = (int64_t)p->L * p->L;
+    std::vector<int8_t> codes;
+    int64_t Q = 0, Nc = 0;
+    if (p->init_codes) {
+        codes.assign(p->init_codes, p->init_codes + N);
+        for (int64_t i = 0; i < N; ++i) {
+            const int c = codes[(size_t)i];
+            if (c < 0 || c > 3) return fail(LAT_EINVAL, "init code outside 0..3");
+            Q += c == 2 ? 1 : (c == 3 ? -1 : 0);
+            Nc += c >= 2;
+        }
+    } else {
+        const int rc = charge_target(p->L, p->n, p->n_charged, &Q, &Nc);
+        if (rc) return rc;
+        seeded_init(p->L, p->seed, (Nc + Q) / 2, (Nc - Q) / 2, codes);
+    }
+    std::vector<uint8_t> dev;
+    to_device_layout(p->L, p->encoding, codes, dev);
+    std::vector<uint32_t> tab;
+    build_threshold_table(p->Delta, p->V, p->J, p->T, tab);
+
+    lattice *h = new lattice();
+    h->L = p->L;
+    h->enc = p->encoding;
+    h->N = N;
+    h->Q = Q;
+    h->Nc = Nc;
+    h->n = p->n;
+    h->Delta = p->Delta;
+    h->V = p->V;
+    h->J = p->J;
+    h->T = p->T;
+    h->seed = p->seed;
+    h->start_sweep = p->start_sweep;
+    h->d_state = d_state;
+    h->d_scratch = (uint8_t *)d_scratch;
+    h->stream = (hipStream_t)hip_stream;
+    h->magic = kMagic;
+
+    hipError_t e = hipMemcpyAsync(d_state, dev.data(), dev.size(), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->d_scratch + kScrTable, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = launch_zero_i64((unsigned long long *)(h->d_scratch + kScrTrack), 10, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // host staging buffers die with this frame
+    if (e != hipSuccess) {
+        h->magic = 0;
+        delete h;
+        return hip_fail(e, "lattice_create");
+    }
+    *out = h;
+    return LAT_OK;
+}
+
+int lattice_sweep(lattice *h, uint32_t sweeps)
+{
+    if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
+    return enqueue_sweeps(h, sweeps, h->stream);
+}
+
+int lattice_sweep_batch(lattice *const *hs, int32_t count, uint32_t sweeps, void *hip_stream)
+{
+    if (count < 0 || (count > 0 && !hs)) return fail(LAT_EINVAL, "bad batch");
+    for (int32_t i = 0; i < count; ++i)
+        if (!live(hs[i])) return fail(LAT_ESTATE, "null or destroyed handle in batch");
+    for (int32_t i = 0; i < count; ++i) {
+        const int rc = enqueue_sweeps(hs[i], sweeps, (hipStream_t)hip_stream);
+        if (rc) return rc;
+    }
+    return LAT_OK;
+}
+
+int lattice_observables(lattice *h, lat_obs *out)
+{
+    if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
+    if (!out) return fail(LAT_EINVAL, "null output");
+    unsigned long long *track = (unsigned long long *)(h->d_scratch + kScrTrack);
+    unsigned long long *obs = (unsigned long long *)(h->d_scratch + kScrObs);
+    hipError_t e = launch_observables(h->d_state, h->L, h->enc, obs, h->stream);
+    int64_t v[10];
+    if (e == hipSuccess) e = hipMemcpyAsync(v, track, sizeof(v), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "lattice_observables");
+    out->sweep = h->done;
+    out->track_nD = v[0];
+    out->track_nV = v[1];
+    out->track_nJ = v[2];
+    out->sum_S = v[3];
+    out->n_charged = v[4];
+    out->bond_SS = v[5];
+    out->bond_ss = v[6];
+    out->M = v[7];
+    out->M_stag = v[8];
+    out->C_stag = v[9];
+    out->E = h->Delta * (double)out->n_charged + h->V * (double)out->bond_SS + 0.25 * h->J * (double)out->bond_ss;
+    return LAT_OK;
+}
+
+int lattice_read_state(lattice *h, int8_t *host_codes)
+{
+    if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
+    if (!host_codes) return fail(LAT_EINVAL, "null output");
+    std::vector<uint8_t> dev(lattice_state_bytes(h->L, h->enc));
+    hipError_t e = hipMemcpyAsync(dev.data(), h->d_state, dev.size(), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "lattice_read_state");
+    from_device_layout(h->L, h->enc, dev, host_codes);
+    return LAT_OK;
+}
+
+int lattice_destroy(lattice *h)
+{
+    if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
+    h->magic = 0;
+    delete h;
+    return LAT_OK;
+}
+
+const char *lattice_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

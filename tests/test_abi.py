@@ -1,0 +1,95 @@
+"""The C-ABI library loads on the CPU, exports every symbol include/lattice.h
+declares, and its host-side logic (charge target, argument checks) agrees
+with the oracle and the header.  No GPU call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+import paper_2301_11735_amd as lat
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lattice.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(lat.LIB_PATH), reason="liblattice.so not built")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lattice_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_exports():
+    assert _declared_functions() == sorted(lat.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    dll = ctypes.CDLL(lat.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(dll, name), name
+
+
+def test_state_and_scratch_sizes():
+    assert lat.state_bytes(32, lat.ENC_INT8) == 1024
+    assert lat.state_bytes(8192, lat.ENC_2BIT) == 8192 * 8192 // 4
+    assert lat.state_bytes(30, lat.ENC_INT8) == 0
+    assert lat.state_bytes(96, lat.ENC_2BIT) == 0      # 2-bit needs L % 64 == 0
+    assert lat.state_bytes(2, lat.ENC_INT8) == 0
+    assert lat.scratch_bytes(32, lat.ENC_INT8) >= 5445 * 4 + 80
+
+
+@pytest.mark.parametrize("L,n,nc", [(32, 0.1, -1), (1024, 0.05, -1), (8192, 0.1, -1), (128, 0.3, -1),
+                                    (4, -0.125, -1), (64, 0.0, 0), (12, 0.37, -1), (16, 0.01, 7)])
+def test_charge_target_matches_oracle(L, n, nc):
+    try:
+        want = oracle.charge_target(L, n, nc)
+    except ValueError:
+        with pytest.raises(lat.LatticeError):
+            lat.charge_target(L, n, nc)
+        return
+    assert lat.charge_target(L, n, nc) == want
+
+
+def _create_rc(**kw):
+    p = lat.LatParams(L=32, encoding=0, n=0.1, Delta=0.25, V=0.5, J=1.0, T=0.8, seed=1, n_charged=-1,
+                      start_sweep=0, init_codes=None)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    h = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(1)  # never dereferenced: validation fails first
+    rc = lat.lib().lattice_create(ctypes.byref(p), ctypes.addressof(buf), 1 << 40, ctypes.addressof(buf),
+                                  1 << 40, None, ctypes.byref(h))
+    return rc, lat.lib().lattice_last_error().decode(), h.value
+
+
+@pytest.mark.parametrize("kw", [dict(L=30), dict(L=0), dict(L=96, encoding=1), dict(encoding=7),
+                                dict(T=0.0), dict(T=-1.0), dict(Delta=float("inf")), dict(J=float("nan")),
+                                dict(n=1.5), dict(n=0.5, n_charged=4), dict(n_charged=2000)])
+def test_create_rejects_invalid_arguments_before_touching_memory(kw):
+    rc, msg, h = _create_rc(**kw)
+    assert rc == lat.LAT_EINVAL and msg and h is None
+
+
+def test_create_rejects_small_buffers():
+    p = lat.LatParams(L=32, encoding=0, n=0.1, Delta=0.25, V=0.5, J=1.0, T=0.8, seed=1, n_charged=-1,
+                      start_sweep=0, init_codes=None)
+    h = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(1)
+    rc = lat.lib().lattice_create(ctypes.byref(p), ctypes.addressof(buf), 1023, ctypes.addressof(buf), 1 << 20,
+                                  None, ctypes.byref(h))
+    assert rc == lat.LAT_ENOMEM
+    rc = lat.lib().lattice_create(ctypes.byref(p), ctypes.addressof(buf), 1024, ctypes.addressof(buf), 100,
+                                  None, ctypes.byref(h))
+    assert rc == lat.LAT_ENOMEM
+
+
+def test_calls_on_null_handles_fail_cleanly():
+    L = lat.lib()
+    assert L.lattice_sweep(None, 1) == lat.LAT_ESTATE
+    assert L.lattice_destroy(None) == lat.LAT_ESTATE
+    assert L.lattice_observables(None, ctypes.byref(lat.LatObs())) == lat.LAT_ESTATE
+    assert L.lattice_sweep_batch(None, 1, 1, None) == lat.LAT_EINVAL
+    assert L.lattice_sweep_batch(None, 0, 1, None) == lat.LAT_OK

@@ -1,0 +1,174 @@
+"""GPU parity: the HIP path (through the C-ABI) against the sequential oracle.
+
+The bar is bit-exact: the state codes, all seven integer observables and the
+incremental energy tracker must be identical after every observed sweep.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2301_11735_amd as lat
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _pair(spec: workloads.LatticeSpec, init_codes=None, start_sweep=0):
+    g = lat.Lattice(spec.L, spec.n, spec.Delta, spec.V, spec.J, spec.T, spec.seed, encoding=spec.encoding,
+                    n_charged=spec.n_charged, start_sweep=start_sweep, init_codes=init_codes)
+    o = oracle.OracleLattice(spec.L, spec.n, spec.Delta, spec.V, spec.J, spec.T, spec.seed,
+                             n_charged=spec.n_charged, start_sweep=start_sweep, codes=init_codes)
+    return g, o
+
+
+def _assert_same(g, o, where=""):
+    gs = g.read_state()
+    if not np.array_equal(gs, o.codes):
+        bad = np.flatnonzero(gs != o.codes)
+        raise AssertionError(f"{where}: {bad.size} sites differ, first at {bad[:8].tolist()}")
+    go = g.observables()
+    assert go.ints() == o.observables().tolist(), where
+    assert [go.track_nD, go.track_nV, go.track_nJ] == o.track.tolist(), where
+    assert go.E == o.energy(), where
+
+
+def _run_parity(spec, checkpoints):
+    _say(f"case L={spec.L} enc={spec.encoding} n={spec.n} T={spec.T} seed={spec.seed} checkpoints={checkpoints}")
+    g, o = _pair(spec)
+    _assert_same(g, o, "init")
+    done = 0
+    for c in checkpoints:
+        g.sweep(c - done)
+        o.sweeps(c - done)
+        done = c
+        _assert_same(g, o, f"after {c} sweeps")
+    g.destroy()
+
+
+SMALL = workloads.SMALL
+
+
+@pytest.mark.parametrize("spec", [
+    SMALL.with_(L=4, n=0.125),
+    SMALL.with_(L=8, n=-0.1, seed=9),
+    SMALL.with_(L=12, n=0.2, seed=10),          # L/4 odd: a Philox call spans two rows
+    SMALL.with_(L=20, T=0.3, seed=11),
+    SMALL,                                      # L=32, n=0.1 (sum S = 102)
+    SMALL.with_(L=100, Delta=-0.7, V=-0.3, T=1.7, seed=12),
+    SMALL.with_(L=256, seed=13),
+], ids=lambda s: f"int8-L{s.L}")
+def test_int8_matches_oracle(spec):
+    _run_parity(spec, [1, 2, 5, 10, 25])
+
+
+@pytest.mark.parametrize("spec", [
+    SMALL.with_(L=64, encoding=1),
+    SMALL.with_(L=128, encoding=1, n=0.3, T=0.4, seed=21),
+    SMALL.with_(L=192, encoding=1, Delta=0.9, V=-0.8, T=2.2, seed=22),   # 3 words per class row
+    SMALL.with_(L=256, encoding=1, n=-0.2, seed=23),
+    SMALL.with_(L=512, encoding=1, T=1.2, seed=24),
+], ids=lambda s: f"2bit-L{s.L}")
+def test_2bit_matches_oracle(spec):
+    _run_parity(spec, [1, 2, 5, 10, 25])
+
+
+def test_small_config_observable_series():
+    """SMALL: observables every 10 sweeps for the first 500 sweeps."""
+    _say("case SMALL series")
+    g, o = _pair(SMALL)
+    for k in range(50):
+        g.sweep(10)
+        o.sweeps(10)
+        go = g.observables()
+        assert go.ints() == o.observables().tolist(), k
+        assert [go.track_nD, go.track_nV, go.track_nJ] == o.track.tolist(), k
+    _assert_same(g, o, "end")
+
+
+def test_int8_and_2bit_run_the_same_chain():
+    spec = SMALL.with_(L=128, seed=31)
+    _say("case int8 vs 2bit L=128")
+    a = lat.Lattice(spec.L, spec.n, spec.Delta, spec.V, spec.J, spec.T, spec.seed, encoding=0)
+    b = lat.Lattice(spec.L, spec.n, spec.Delta, spec.V, spec.J, spec.T, spec.seed, encoding=1)
+    for _ in range(4):
+        a.sweep(7)
+        b.sweep(7)
+        assert np.array_equal(a.read_state(), b.read_state())
+        assert a.observables().as_dict() == b.observables().as_dict()
+
+
+@pytest.mark.parametrize("encoding,L", [(0, 32), (1, 128)])
+def test_resume_from_read_state_is_bit_exact(encoding, L):
+    _say(f"case resume enc={encoding} L={L}")
+    spec = SMALL.with_(L=L, encoding=encoding, seed=41)
+    full = lat.Lattice(spec.L, spec.n, spec.Delta, spec.V, spec.J, spec.T, spec.seed, encoding=encoding)
+    full.sweep(30)
+    part = lat.Lattice(spec.L, spec.n, spec.Delta, spec.V, spec.J, spec.T, spec.seed, encoding=encoding)
+    part.sweep(12)
+    mid = part.read_state()
+    resumed = lat.Lattice(spec.L, spec.n, spec.Delta, spec.V, spec.J, spec.T, spec.seed, encoding=encoding,
+                          start_sweep=12, init_codes=mid)
+    resumed.sweep(18)
+    assert np.array_equal(full.read_state(), resumed.read_state())
+
+
+def test_sweep_batch_equals_separate_sweeps():
+    _say("case batch")
+    specs = [SMALL.with_(L=L, encoding=e, seed=50 + i, T=0.5 + 0.3 * i)
+             for i, (L, e) in enumerate([(32, 0), (64, 1), (128, 1), (20, 0)])]
+    batch = [lat.Lattice(s.L, s.n, s.Delta, s.V, s.J, s.T, s.seed, encoding=s.encoding) for s in specs]
+    alone = [lat.Lattice(s.L, s.n, s.Delta, s.V, s.J, s.T, s.seed, encoding=s.encoding) for s in specs]
+    lat.sweep_batch(batch, 9)
+    for a in alone:
+        a.sweep(9)
+    for a, b in zip(alone, batch):
+        assert np.array_equal(a.read_state(), b.read_state())
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n=0.0, n_charged=0, Delta=1e6),       # no charges: pure Ising spins
+    dict(n=0.0, n_charged=32 * 32),            # every site charged
+    dict(n=1.0),                               # every site +1: all pairs frozen
+    dict(T=1e-3),                              # quench
+    dict(T=1e6, Delta=0.0, V=0.0, J=0.0),      # everything accepted
+], ids=["no-charge", "all-charged", "all-plus", "cold", "hot"])
+def test_degenerate_cases(kw):
+    spec = SMALL.with_(**kw)
+    _run_parity(spec, [1, 3, 10])
+    spec2 = spec.with_(L=64, encoding=1, n_charged=(64 * 64 if spec.n_charged == 32 * 32 else spec.n_charged))
+    _run_parity(spec2, [1, 3, 10])
+
+
+def test_mid_config_parity_first_sweeps():
+    """MID (L=1024, int8): bit-exact state and observables for the first sweeps."""
+    _run_parity(workloads.MID, [1, 2, 3])
+
+
+def test_large_config_parity_first_sweep():
+    """LARGE (L=8192, 2-bit) in the launch configuration the benchmark times:
+    the full state after one sweep, bit-exact."""
+    _run_parity(workloads.LARGE, [1])
+
+
+def test_large_config_invariants():
+    """LARGE over 100 sweeps: charge exact and tracker == recomputed energy."""
+    spec = workloads.LARGE
+    _say("case LARGE invariants")
+    g = lat.Lattice(spec.L, spec.n, spec.Delta, spec.V, spec.J, spec.T, spec.seed, encoding=spec.encoding)
+    Q, Nc = lat.charge_target(spec.L, spec.n)
+    o0 = g.observables()
+    assert o0.sum_S == Q and o0.n_charged == Nc
+    for _ in range(4):
+        g.sweep(25)
+        o = g.observables()
+        assert o.sum_S == Q
+        assert o.track_nD == o.n_charged - o0.n_charged
+        assert o.track_nV == o.bond_SS - o0.bond_SS
+        assert o.track_nJ == o.bond_ss - o0.bond_ss
