@@ -6,6 +6,13 @@
 // partners b = a + D.  No updated site neighbours another updated site, so
 // every pair reads only sites nobody writes in the phase and the pairs are
 // independent; the phase equals their sequential composition.
+//
+// Per pair the work is table driven (both tables staged in LDS once per
+// block): the pair state st = code_a | code_b<<2 and the choice j select a
+// transition entry (section 3.1's same-charge sets); one v_dot4 of that
+// entry with the packed neighbour sums gives the index of the move's
+// energy-change triple in the threshold table; the acceptance test is one
+// unsigned compare.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -15,49 +22,62 @@
 namespace lat {
 namespace {
 
-// S and sigma of a site code: 0 -> (0,+1), 1 -> (0,-1), 2 -> (+1,0), 3 -> (-1,0).
-__device__ __forceinline__ int charge_of(uint32_t c) { return (c & 2u) ? 1 - 2 * (int)(c & 1u) : 0; }
-__device__ __forceinline__ int spin_of(uint32_t c) { return (c & 2u) ? 0 : 1 - 2 * (int)(c & 1u); }
+constexpr uint32_t kM5 = 0x55555555u;  // bit 0 of every 2-bit field
+constexpr uint32_t kM3 = 0x33333333u;  // low 2 bits of every nibble
+constexpr uint32_t kM0F = 0x0F0F0F0Fu; // low nibble of every byte
 
-// Same-charge pair sets of section 3.1 in the paper's listing order, one
-// 4-bit entry per configuration (code_a | code_b << 2), entry j at bits 4j:
-//   q=+1: (2,0) (2,1) (0,2) (1,2)
-//   q= 0: (2,3) (3,2) (0,0) (1,1) (0,1) (1,0)
-//   q=-1: (3,0) (3,1) (0,3) (1,3)
-constexpr uint32_t kSetPlus1 = 0x9862u;
-constexpr uint32_t kSetZero = 0x1450BEu;
-constexpr uint32_t kSetMinus1 = 0xDC73u;
+constexpr int charge_c(int c) { return (c & 2) ? 1 - 2 * (c & 1) : 0; }
 
-// Coupled-pair Metropolis step (section 3.1) for codes (ca, cb) whose
-// neighbour sums are (sSa, sGa) and (sSb, sGb).  uc picks the configuration,
-// ua is the acceptance draw.  Returns the new codes through na, nb and adds
-// the accepted energy-change triple to (tD, tV, tJ).
-__device__ __forceinline__ void pair_move(uint32_t ca, uint32_t cb, int sSa, int sGa, int sSb, int sGb,
-                                          uint32_t uc, uint32_t ua, const uint32_t *__restrict__ thr,
-                                          uint32_t &na, uint32_t &nb, int &tD, int &tV, int &tJ)
+// Number of configurations k_q of the same-charge set for every pair state
+// (3 bits per state): 6 for q = 0, 4 for q = +-1, and 1 for the frozen
+// |q| = 2 states, whose single entry is the null move.
+constexpr uint64_t make_kq()
 {
-    na = ca;
-    nb = cb;
-    const int Sa = charge_of(ca), Sb = charge_of(cb);
-    const int q = Sa + Sb;
-    if (q == 2 || q == -2) return;  // frozen pair
-    const uint32_t kq = (q == 0) ? 6u : 4u;
-    const uint32_t j = ((uc >> 8) * kq) >> 24;
-    const uint32_t set = (q == 1) ? kSetPlus1 : ((q == 0) ? kSetZero : kSetMinus1);
-    const uint32_t e = (set >> (4u * j)) & 15u;
-    const uint32_t a1 = e & 3u, b1 = e >> 2;
-    const int Sa1 = charge_of(a1), Sb1 = charge_of(b1);
-    const int nD = Sa1 * Sa1 + Sb1 * Sb1 - Sa * Sa - Sb * Sb;
-    const int nV = (Sa1 - Sa) * sSa + (Sb1 - Sb) * sSb;
-    const int nJ = (spin_of(a1) - spin_of(ca)) * sGa + (spin_of(b1) - spin_of(cb)) * sGb;
-    const uint32_t t = thr[(nD + 2) * (kTabV * kTabJ) + (nV + 16) * kTabJ + (nJ + 16)];
-    if (t == 0xFFFFFFFFu || ua < t) {
-        na = a1;
-        nb = b1;
-        tD += nD;
-        tV += nV;
-        tJ += nJ;
+    uint64_t v = 0;
+    for (int st = 0; st < 16; ++st) {
+        const int q = charge_c(st & 3) + charge_c(st >> 2);
+        const uint64_t kq = (q == 2 || q == -2) ? 1 : (q == 0 ? 6 : 4);
+        v |= kq << (3 * st);
     }
+    return v;
+}
+constexpr uint64_t kKq = make_kq();
+
+__device__ __forceinline__ void stage_tables(uint2 *s_tab, uint2 *s_trans, const uint2 *__restrict__ g_tab,
+                                             const uint2 *__restrict__ g_trans)
+{
+    for (int i = threadIdx.x; i < kDevTabEntries; i += blockDim.x) s_tab[i] = g_tab[i];
+    for (int i = threadIdx.x; i < kTransEntries; i += blockDim.x) s_trans[i] = g_trans[i];
+    __syncthreads();
+}
+
+// One coupled-pair Metropolis step (section 3.1).  bpack holds the neighbour
+// sums (sumS_a+4, sumS_b+4, sumsig_a+4, sumsig_b+4) as bytes; uc picks the
+// configuration j = floor(k_q * (uc >> 8) / 2^24); ua is the acceptance draw,
+// compared as min(ua, 2^32-2) < thr so that the reserved "always" threshold
+// 2^32-1 accepts every draw.  Returns the new pair state and adds the
+// accepted move's packed triple to `packed`.
+__device__ __forceinline__ uint32_t pair_step(uint32_t st, uint32_t bpack, uint32_t uc, uint32_t ua,
+                                              const uint2 *__restrict__ s_trans, const uint2 *__restrict__ s_tab,
+                                              uint32_t &packed)
+{
+    const uint32_t kq = (uint32_t)(kKq >> (3u * st)) & 7u;
+    const uint32_t j = ((uc >> 8) * kq) >> 24;
+    const uint2 tr = s_trans[st * 6u + j];
+    const int idx = __builtin_amdgcn_sdot4((int)tr.x, (int)bpack, (int)(tr.y & 0xFFFFu), false);
+    const uint2 e = s_tab[idx];
+    const bool acc = min(ua, 0xFFFFFFFEu) < e.x;
+    packed += acc ? e.y : 0u;
+    return acc ? (tr.y >> 16) : st;
+}
+
+// Per-thread tracker: counts and biased sums of the accepted triples.
+__device__ __forceinline__ void unpack_tracker(uint32_t packed, int (&tr)[3])
+{
+    const int cnt = (int)(packed >> 27);
+    tr[0] += (int)((packed >> 20) & 127u) - 2 * cnt;
+    tr[1] += (int)((packed >> 10) & 1023u) - 16 * cnt;
+    tr[2] += (int)(packed & 1023u) - 16 * cnt;
 }
 
 template <int K, typename T>
@@ -86,16 +106,28 @@ __device__ __forceinline__ void block_reduce_add(T (&v)[K], unsigned long long *
 // ---------------------------------------------------------------------------
 // int8 layout: one code per byte, row-major.  Thread t owns Philox call t,
 // i.e. pairs 2t and 2t+1 (words 0,1 and 2,3 of the call).
+//
+// Neighbour contribution of a code c to the packed sums: byte 0 (a side) or
+// byte 1 (b side) gets 1+S(c), byte 2 or byte 3 gets 1+sigma(c); the values
+// per code are the bytes of kVS = {1,1,2,0} and kVG = {2,0,1,1}.
+constexpr uint32_t kVS = 0x00020101u;
+constexpr uint32_t kVG = 0x01010002u;
+__device__ __forceinline__ uint32_t contrib_a(uint32_t c) { return __builtin_amdgcn_perm(kVG, kVS, 0x0C040C00u + c * 0x00010001u); }
+__device__ __forceinline__ uint32_t contrib_b(uint32_t c) { return __builtin_amdgcn_perm(kVG, kVS, 0x040C000Cu + c * 0x01000100u); }
+
 __global__ void __launch_bounds__(256) k_phase_int8(PhaseArgs a)
 {
+    __shared__ uint2 s_tab[kDevTabEntries];
+    __shared__ uint2 s_trans[kTransEntries];
+    stage_tables(s_tab, s_trans, a.dev_tab, a.trans);
     const int L = a.L, Lq = L >> 2;
     const uint32_t n_calls = (uint32_t)L * (uint32_t)L / 16u;
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    int8_t *st = (int8_t *)a.state;
+    const int Dx = a.r + 4 * a.m, Dy = 1 + 2 * a.k;
     int tr[3] = {0, 0, 0};
-    if (t < n_calls) {
-        int8_t *st = (int8_t *)a.state;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_calls; t += gridDim.x * blockDim.x) {
         const u32x4 w = philox4x32_10(a.s_lo, (uint32_t)a.p, t, a.s_hi, a.key0, a.key1);
-        const int Dx = a.r + 4 * a.m, Dy = 1 + 2 * a.k;
+        uint32_t packed = 0;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const uint32_t pi = 2u * t + (uint32_t)h;
@@ -110,20 +142,19 @@ __global__ void __launch_bounds__(256) k_phase_int8(PhaseArgs a)
             const int ybu = yb == 0 ? L - 1 : yb - 1, ybd = yb == L - 1 ? 0 : yb + 1;
             const size_t ia = (size_t)y * L + x, ib = (size_t)yb * L + xb;
             const uint32_t ca = (uint32_t)st[ia], cb = (uint32_t)st[ib];
-            const uint32_t n0 = st[(size_t)y * L + xl], n1 = st[(size_t)y * L + xr];
-            const uint32_t n2 = st[(size_t)yu * L + x], n3 = st[(size_t)yd * L + x];
-            const uint32_t m0 = st[(size_t)yb * L + xbl], m1 = st[(size_t)yb * L + xbr];
-            const uint32_t m2 = st[(size_t)ybu * L + xb], m3 = st[(size_t)ybd * L + xb];
-            const int sSa = charge_of(n0) + charge_of(n1) + charge_of(n2) + charge_of(n3);
-            const int sGa = spin_of(n0) + spin_of(n1) + spin_of(n2) + spin_of(n3);
-            const int sSb = charge_of(m0) + charge_of(m1) + charge_of(m2) + charge_of(m3);
-            const int sGb = spin_of(m0) + spin_of(m1) + spin_of(m2) + spin_of(m3);
-            uint32_t na, nb;
-            pair_move(ca, cb, sSa, sGa, sSb, sGb, h ? w.z : w.x, h ? w.w : w.y, a.thr, na, nb, tr[0], tr[1],
-                      tr[2]);
-            if (na != ca) st[ia] = (int8_t)na;
-            if (nb != cb) st[ib] = (int8_t)nb;
+            const uint32_t bpack =
+                contrib_a(st[(size_t)y * L + xl]) + contrib_a(st[(size_t)y * L + xr]) +
+                contrib_a(st[(size_t)yu * L + x]) + contrib_a(st[(size_t)yd * L + x]) +
+                contrib_b(st[(size_t)yb * L + xbl]) + contrib_b(st[(size_t)yb * L + xbr]) +
+                contrib_b(st[(size_t)ybu * L + xb]) + contrib_b(st[(size_t)ybd * L + xb]);
+            const uint32_t s0 = ca | (cb << 2);
+            const uint32_t ns = pair_step(s0, bpack, h ? w.z : w.x, h ? w.w : w.y, s_trans, s_tab, packed);
+            if (ns != s0) {
+                st[ia] = (int8_t)(ns & 3u);
+                st[ib] = (int8_t)(ns >> 2);
+            }
         }
+        unpack_tracker(packed, tr);
     }
     block_reduce_add<3>(tr, a.track);
 }
@@ -148,77 +179,132 @@ __device__ __forceinline__ uint32_t load16(const uint32_t *__restrict__ row, int
     return sh ? __builtin_amdgcn_alignbit(w1, w0, 2u * (uint32_t)sh) : w0;
 }
 
-__device__ __forceinline__ void sums_at(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, int sh, int &sS,
-                                        int &sG)
+// Neighbour sums of 16 sites from their 4 neighbour words, SWAR: per code
+// the values 1+S in {0,1,2} and 1+sigma in {0,1,2} as 2-bit fields, split
+// into even and odd sites so that the 4-term sums (at most 8) fit nibbles.
+struct SideSums {
+    uint32_t ES, OS, EG, OG;  // nibble u: sum over neighbours of site 2u (E) or 2u+1 (O)
+};
+
+__device__ __forceinline__ SideSums side_sums(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3)
 {
-    const uint32_t c0 = (w0 >> sh) & 3u, c1 = (w1 >> sh) & 3u, c2 = (w2 >> sh) & 3u, c3 = (w3 >> sh) & 3u;
-    sS = charge_of(c0) + charge_of(c1) + charge_of(c2) + charge_of(c3);
-    sG = spin_of(c0) + spin_of(c1) + spin_of(c2) + spin_of(c3);
+    SideSums s{0u, 0u, 0u, 0u};
+    const uint32_t ws[4] = {w0, w1, w2, w3};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t h = (ws[i] >> 1) & kM5, l = ws[i] & kM5;
+        const uint32_t vS = ((h & ~l) << 1) | (h ^ kM5);        // code 2 -> 2, 3 -> 0, spins -> 1
+        const uint32_t vG = (((h | l) ^ kM5) << 1) | h;          // code 0 -> 2, 1 -> 0, charges -> 1
+        s.ES += vS & kM3;
+        s.OS += (vS >> 2) & kM3;
+        s.EG += vG & kM3;
+        s.OG += (vG >> 2) & kM3;
+    }
+    return s;
 }
 
-__global__ void __launch_bounds__(1024) k_phase_2bit(PhaseArgs a)
+// 4x4 byte transpose: out[k] = (r0.byte k, r1.byte k, r2.byte k, r3.byte k).
+__device__ __forceinline__ void transpose4(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t r3, uint32_t &c0,
+                                           uint32_t &c1, uint32_t &c2, uint32_t &c3)
 {
-    extern __shared__ uint32_t xch[];
+    const uint32_t p01lo = __builtin_amdgcn_perm(r1, r0, 0x05010400u);
+    const uint32_t p01hi = __builtin_amdgcn_perm(r1, r0, 0x07030602u);
+    const uint32_t p23lo = __builtin_amdgcn_perm(r3, r2, 0x05010400u);
+    const uint32_t p23hi = __builtin_amdgcn_perm(r3, r2, 0x07030602u);
+    c0 = __builtin_amdgcn_perm(p23lo, p01lo, 0x05040100u);
+    c1 = __builtin_amdgcn_perm(p23lo, p01lo, 0x07060302u);
+    c2 = __builtin_amdgcn_perm(p23hi, p01hi, 0x05040100u);
+    c3 = __builtin_amdgcn_perm(p23hi, p01hi, 0x07060302u);
+}
+
+__global__ void __launch_bounds__(1024) k_phase_2bit(PhaseArgs a, int rows_per_block)
+{
+    __shared__ uint2 s_tab[kDevTabEntries];
+    __shared__ uint2 s_trans[kTransEntries];
+    extern __shared__ uint32_t xch[];  // 2 x blockDim (double buffered)
+    stage_tables(s_tab, s_trans, a.dev_tab, a.trans);
+
     const int L = a.L, W = L >> 6, H = L >> 1, Lq = L >> 2;
-    const int rows_per_block = blockDim.x / W;
     const int rr = threadIdx.x / W, j = threadIdx.x - rr * W;
-    const int Y = blockIdx.x * rows_per_block + rr;
+    const int n_groups = H / rows_per_block;
     uint32_t *st = (uint32_t *)a.state;
     const size_t csz = (size_t)H * W;
     const int p = a.p;
     const int pb = (p + a.r) & 3, carry = (p + a.r) >> 2;
     int dX = a.m + carry;
     if (dX >= Lq) dX -= Lq;
-    int Yb = Y + a.k;
-    if (Yb >= H) Yb -= H;
     int Xb = 16 * j + dX;
     if (Xb >= Lq) Xb -= Lq;
-
-    // a side: class (p, 0) row Y word j and its four neighbour words
-    uint32_t *rowA = st + (size_t)p * csz + (size_t)Y * W;
-    const uint32_t A0 = rowA[j];
-    const uint32_t AL = p > 0 ? st[(size_t)(p - 1) * csz + (size_t)Y * W + j]
-                              : load16(st + 3 * csz + (size_t)Y * W, W, 16 * j == 0 ? Lq - 1 : 16 * j - 1);
-    const uint32_t AR = p < 3 ? st[(size_t)(p + 1) * csz + (size_t)Y * W + j]
-                              : load16(st + (size_t)Y * W, W, 16 * j + 1 == Lq ? 0 : 16 * j + 1);
-    const uint32_t AU = st[(size_t)(4 + p) * csz + (size_t)(Y == 0 ? H - 1 : Y - 1) * W + j];
-    const uint32_t AD = st[(size_t)(4 + p) * csz + (size_t)Y * W + j];
-    // b side: class (pb, 1) row Yb from class position Xb, and neighbours
-    uint32_t *rowB = st + (size_t)(4 + pb) * csz + (size_t)Yb * W;
-    const uint32_t B0 = load16(rowB, W, Xb);
-    const uint32_t BL = pb > 0 ? load16(st + (size_t)(4 + pb - 1) * csz + (size_t)Yb * W, W, Xb)
-                               : load16(st + 7 * csz + (size_t)Yb * W, W, Xb == 0 ? Lq - 1 : Xb - 1);
-    const uint32_t BR = pb < 3 ? load16(st + (size_t)(4 + pb + 1) * csz + (size_t)Yb * W, W, Xb)
-                               : load16(st + 4 * csz + (size_t)Yb * W, W, Xb + 1 == Lq ? 0 : Xb + 1);
-    const uint32_t BU = load16(st + (size_t)pb * csz + (size_t)Yb * W, W, Xb);
-    const uint32_t BD = load16(st + (size_t)pb * csz + (size_t)(Yb + 1 == H ? 0 : Yb + 1) * W, W, Xb);
+    const int jb = Xb >> 4, shb = Xb & 15;
+    const int jw_out = jb + 1 == W ? 0 : jb + 1;
+    const int j_next = j + 1 == W ? 0 : j + 1;
+    // class rows of the a side and the b side (row offsets added per group)
+    uint32_t *cA0 = st + (size_t)p * csz;
+    const uint32_t *cAL = p > 0 ? st + (size_t)(p - 1) * csz : st + 3 * csz;
+    const uint32_t *cAR = p < 3 ? st + (size_t)(p + 1) * csz : st;
+    const uint32_t *cAV = st + (size_t)(4 + p) * csz;
+    uint32_t *cB0 = st + (size_t)(4 + pb) * csz;
+    const uint32_t *cBL = pb > 0 ? st + (size_t)(4 + pb - 1) * csz : st + 7 * csz;
+    const uint32_t *cBR = pb < 3 ? st + (size_t)(4 + pb + 1) * csz : st + 4 * csz;
+    const uint32_t *cBV = st + (size_t)pb * csz;
+    const int xAL = p > 0 ? 16 * j : (j == 0 ? Lq - 1 : 16 * j - 1);
+    const int xAR = p < 3 ? 16 * j : 16 * j + 1;
+    const int xBL = pb > 0 ? Xb : (Xb == 0 ? Lq - 1 : Xb - 1);
+    const int xBR = pb < 3 ? Xb : (Xb + 1 == Lq ? 0 : Xb + 1);
 
     int tr[3] = {0, 0, 0};
-    uint32_t Anew = A0, Bnew = B0;
-    const uint32_t call0 = (uint32_t)Y * (uint32_t)(Lq >> 1) + 8u * (uint32_t)j;
-    for (int c = 0; c < 8; ++c) {
-        const u32x4 w = philox4x32_10(a.s_lo, (uint32_t)p, call0 + (uint32_t)c, a.s_hi, a.key0, a.key1);
+    int buf = 0;
+    for (int g = blockIdx.x; g < n_groups; g += gridDim.x, buf ^= 1) {
+        const int Y = g * rows_per_block + rr;
+        int Yb = Y + a.k;
+        if (Yb >= H) Yb -= H;
+        const size_t ro = (size_t)Y * W, rob = (size_t)Yb * W;
+        const uint32_t A0 = cA0[ro + j];
+        const uint32_t AL = load16(cAL + ro, W, xAL);
+        const uint32_t AR = load16(cAR + ro, W, xAR);
+        const uint32_t AU = cAV[(size_t)(Y == 0 ? H - 1 : Y - 1) * W + j];
+        const uint32_t AD = cAV[ro + j];
+        const uint32_t B0 = load16(cB0 + rob, W, Xb);
+        const uint32_t BL = load16(cBL + rob, W, xBL);
+        const uint32_t BR = load16(cBR + rob, W, xBR);
+        const uint32_t BU = load16(cBV + rob, W, Xb);
+        const uint32_t BD = load16(cBV + (size_t)(Yb + 1 == H ? 0 : Yb + 1) * W, W, Xb);
+
+        const SideSums sa = side_sums(AL, AR, AU, AD);
+        const SideSums sb = side_sums(BL, BR, BU, BD);
+        // bpack[t] = (sumS_a+4, sumS_b+4, sumsig_a+4, sumsig_b+4) of site t;
+        // group t&3 comes from one nibble plane, byte t>>2 within it.
+        uint32_t bp[16];
+        transpose4(sa.ES & kM0F, sb.ES & kM0F, sa.EG & kM0F, sb.EG & kM0F, bp[0], bp[4], bp[8], bp[12]);
+        transpose4(sa.OS & kM0F, sb.OS & kM0F, sa.OG & kM0F, sb.OG & kM0F, bp[1], bp[5], bp[9], bp[13]);
+        transpose4((sa.ES >> 4) & kM0F, (sb.ES >> 4) & kM0F, (sa.EG >> 4) & kM0F, (sb.EG >> 4) & kM0F, bp[2],
+                   bp[6], bp[10], bp[14]);
+        transpose4((sa.OS >> 4) & kM0F, (sb.OS >> 4) & kM0F, (sa.OG >> 4) & kM0F, (sb.OG >> 4) & kM0F, bp[3],
+                   bp[7], bp[11], bp[15]);
+
+        uint32_t Anew = 0u, Bnew = 0u, packed = 0u;
+        const uint32_t call0 = (uint32_t)Y * (uint32_t)(Lq >> 1) + 8u * (uint32_t)j;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int sh = 2 * (2 * c + h);
-            const uint32_t ca = (A0 >> sh) & 3u, cb = (B0 >> sh) & 3u;
-            int sSa, sGa, sSb, sGb;
-            sums_at(AL, AR, AU, AD, sh, sSa, sGa);
-            sums_at(BL, BR, BU, BD, sh, sSb, sGb);
-            uint32_t na, nb;
-            pair_move(ca, cb, sSa, sGa, sSb, sGb, h ? w.z : w.x, h ? w.w : w.y, a.thr, na, nb, tr[0], tr[1],
-                      tr[2]);
-            Anew ^= (na ^ ca) << sh;
-            Bnew ^= (nb ^ cb) << sh;
+        for (int c = 0; c < 8; ++c) {
+            const u32x4 w = philox4x32_10(a.s_lo, (uint32_t)p, call0 + (uint32_t)c, a.s_hi, a.key0, a.key1);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int t = 2 * c + h;
+                const uint32_t s0 = ((A0 >> (2 * t)) & 3u) | (((B0 >> (2 * t)) & 3u) << 2);
+                const uint32_t ns = pair_step(s0, bp[t], h ? w.z : w.x, h ? w.w : w.y, s_trans, s_tab, packed);
+                Anew |= (ns & 3u) << (2 * t);
+                Bnew |= (ns >> 2) << (2 * t);
+            }
         }
+        unpack_tracker(packed, tr);
+        cA0[ro + j] = Anew;
+        uint32_t *x = xch + buf * blockDim.x;
+        x[threadIdx.x] = Bnew;
+        __syncthreads();
+        const uint32_t nxt = x[rr * W + j_next];
+        const uint32_t word = shb ? __builtin_amdgcn_alignbit(nxt, Bnew, 32u - 2u * (uint32_t)shb) : nxt;
+        cB0[rob + jw_out] = word;
     }
-    rowA[j] = Anew;
-    xch[threadIdx.x] = Bnew;
-    __syncthreads();
-    const uint32_t nxt = xch[rr * W + (j + 1 == W ? 0 : j + 1)];
-    const int jb = Xb >> 4, shb = Xb & 15;
-    const uint32_t word = shb ? __builtin_amdgcn_alignbit(nxt, Bnew, 32u - 2u * (uint32_t)shb) : nxt;
-    rowB[jb + 1 == W ? 0 : jb + 1] = word;
     block_reduce_add<3>(tr, a.track);
 }
 
@@ -231,6 +317,9 @@ __global__ void k_zero_i64(unsigned long long *p, int n)
 
 // Observable sums: sum S, sum S^2, bonds S S, bonds sigma sigma, sum sigma,
 // staggered sigma, staggered S.  Bonds (x,y)-(x+1,y) and (x,y)-(x,y+1).
+__device__ __forceinline__ int spin_of(uint32_t c) { return (c & 2u) ? 0 : 1 - 2 * (int)(c & 1u); }
+__device__ __forceinline__ int charge_of(uint32_t c) { return (c & 2u) ? 1 - 2 * (int)(c & 1u) : 0; }
+
 __global__ void __launch_bounds__(256) k_obs_int8(const int8_t *__restrict__ st, int L,
                                                   unsigned long long *obs)
 {
@@ -253,6 +342,16 @@ __global__ void __launch_bounds__(256) k_obs_int8(const int8_t *__restrict__ st,
     block_reduce_add<7>(v, obs);
 }
 
+// Bond sums of 16 sites (h, l bit planes) with 16 partner sites (hp, lp):
+// S S = +1 for equal charges, -1 for opposite; sigma sigma likewise for spins.
+__device__ __forceinline__ void bond_sums(uint32_t h, uint32_t l, uint32_t hp, uint32_t lp, int &bSS, int &bss)
+{
+    const uint32_t diff = l ^ lp;
+    const uint32_t cc = h & hp, mm = (h | hp) ^ kM5;  // both charged / both spins
+    bSS += __popc(cc & ~diff) - __popc(cc & diff);
+    bss += __popc(mm & ~diff) - __popc(mm & diff);
+}
+
 __global__ void __launch_bounds__(256) k_obs_2bit(const uint32_t *__restrict__ st, int L,
                                                   unsigned long long *obs)
 {
@@ -271,27 +370,37 @@ __global__ void __launch_bounds__(256) k_obs_2bit(const uint32_t *__restrict__ s
                                             16 * j + 1 == Lq ? 0 : 16 * j + 1);
         const uint32_t wd = cy == 0 ? st[i + 4 * csz]
                                     : st[(size_t)cx * csz + (size_t)(Y + 1 == H ? 0 : Y + 1) * W + j];
+        const uint32_t h = (w >> 1) & kM5, l = w & kM5;
+        const int sumS = __popc(h & ~l) - __popc(h & l);
+        const int sumG = __popc((h | l) ^ kM5) - __popc(l & ~h);
+        int bSS = 0, bss = 0;
+        bond_sums(h, l, (wr >> 1) & kM5, wr & kM5, bSS, bss);
+        bond_sums(h, l, (wd >> 1) & kM5, wd & kM5, bSS, bss);
         const int sg = ((cx + cy) & 1) ? -1 : 1;
-        int s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const uint32_t a = (w >> (2 * t)) & 3u, r = (wr >> (2 * t)) & 3u, d = (wd >> (2 * t)) & 3u;
-            const int S = charge_of(a), G = spin_of(a);
-            s0 += S;
-            s1 += S * S;
-            s2 += S * (charge_of(r) + charge_of(d));
-            s3 += G * (spin_of(r) + spin_of(d));
-            s4 += G;
-        }
-        v[0] += s0;
-        v[1] += s1;
-        v[2] += s2;
-        v[3] += s3;
-        v[4] += s4;
-        v[5] += sg * s4;
-        v[6] += sg * s0;
+        v[0] += sumS;
+        v[1] += __popc(h);
+        v[2] += bSS;
+        v[3] += bss;
+        v[4] += sumG;
+        v[5] += sg * sumG;
+        v[6] += sg * sumS;
     }
     block_reduce_add<7>(v, obs);
+}
+
+int g_num_cus = 0;
+
+int num_cus()
+{
+    if (g_num_cus == 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            g_num_cus = n;
+        else
+            g_num_cus = 256;
+    }
+    return g_num_cus;
 }
 
 }  // namespace
@@ -300,26 +409,37 @@ __global__ void __launch_bounds__(256) k_obs_2bit(const uint32_t *__restrict__ s
 hipError_t launch_phase_int8(const PhaseArgs &a, hipStream_t s)
 {
     const uint32_t n_calls = (uint32_t)a.L * (uint32_t)a.L / 16u;
-    const uint32_t block = 256, grid = (n_calls + block - 1) / block;
+    const uint32_t block = 256;
+    uint32_t grid = (n_calls + block - 1) / block;
+    const uint32_t cap = 4u * (uint32_t)num_cus();
+    if (grid > cap) grid = cap;
     hipLaunchKernelGGL(k_phase_int8, dim3(grid), dim3(block), 0, s, a);
     return hipGetLastError();
 }
 
-// Rows per block: a power of two <= 32 (so it divides the L/2 = 32W rows)
-// giving about 256 threads; every block holds whole class rows.
-static int rows_per_block_2bit(int W)
+// Rows per block: a power of two <= 32 (so it divides the L/2 = 32W rows);
+// by default the largest giving at most 256 threads.  Every block holds
+// whole class rows.
+static int rows_per_block_2bit(int W, int requested)
 {
     int r = 1;
+    if (requested > 0) {
+        while (r < 32 && 2 * r <= requested && 2 * r * W <= 1024) r *= 2;
+        return r;
+    }
     while (r < 32 && 2 * r * W <= 256) r *= 2;
     return r;
 }
 
-hipError_t launch_phase_2bit(const PhaseArgs &a, hipStream_t s)
+hipError_t launch_phase_2bit(const PhaseArgs &a, const Tuning2Bit &t, hipStream_t s)
 {
     const int W = a.L >> 6, H = a.L >> 1;
-    const int R = rows_per_block_2bit(W);
-    const int block = R * W, grid = H / R;
-    hipLaunchKernelGGL(k_phase_2bit, dim3(grid), dim3(block), (size_t)block * 4u, s, a);
+    const int R = rows_per_block_2bit(W, t.rows_per_block);
+    const int block = R * W;
+    int grid = H / R;
+    const int bpc = t.blocks_per_cu > 0 ? t.blocks_per_cu : 4;
+    if (grid > bpc * num_cus()) grid = bpc * num_cus();
+    hipLaunchKernelGGL(k_phase_2bit, dim3(grid), dim3(block), (size_t)block * 8u, s, a, R);
     return hipGetLastError();
 }
 
@@ -335,7 +455,8 @@ hipError_t launch_observables(const void *state, int L, int encoding, unsigned l
     if (e != hipSuccess) return e;
     const size_t units = encoding == 0 ? (size_t)L * L : (size_t)L * L / 16;
     size_t grid = (units + 255) / 256;
-    if (grid > 4096) grid = 4096;
+    const size_t cap = 8u * (size_t)num_cus();
+    if (grid > cap) grid = cap;
     if (encoding == 0)
         hipLaunchKernelGGL(k_obs_int8, dim3((unsigned)grid), dim3(256), 0, s, (const int8_t *)state, L, obs);
     else

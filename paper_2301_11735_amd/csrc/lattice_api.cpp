@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <thread>
@@ -29,6 +30,7 @@ struct lattice {
     void *d_state = nullptr;
     uint8_t *d_scratch = nullptr;
     hipStream_t stream = nullptr;
+    lat::Tuning2Bit tuning{0, 0};
     uint32_t magic = 0;
 };
 
@@ -140,6 +142,69 @@ void build_threshold_table(double Delta, double V, double J, double T, std::vect
             }
 }
 
+// Device threshold table: the reachable slices nD in {-2, 0, 2}, each entry
+// paired with the packed triple an accepted move adds to the tracker.
+void build_device_table(const std::vector<uint32_t> &tab, std::vector<uint32_t> &dev)
+{
+    dev.assign(2 * (size_t)kDevTabEntries, 0u);
+    for (int s = 0; s < 3; ++s) {
+        const int nD = 2 * s - 2;
+        for (int nV = -16; nV <= 16; ++nV)
+            for (int nJ = -16; nJ <= 16; ++nJ) {
+                const size_t i = (size_t)s * (kTabV * kTabJ) + (size_t)(nV + 16) * kTabJ + (size_t)(nJ + 16);
+                dev[2 * i] = tab[(size_t)(nD + 2) * (kTabV * kTabJ) + (size_t)(nV + 16) * kTabJ + (size_t)(nJ + 16)];
+                dev[2 * i + 1] = (1u << 27) | ((uint32_t)(nD + 2) << 20) | ((uint32_t)(nV + 16) << 10) |
+                                 (uint32_t)(nJ + 16);
+            }
+    }
+}
+
+// Transition table of section 3.1's coupled-pair move.  For pair state
+// st = code_a | code_b << 2 and choice j < k_q: the j-th configuration of the
+// same-charge set in the paper's listing order,
+//   q=+1: (2,0) (2,1) (0,2) (1,2)
+//   q= 0: (2,3) (3,2) (0,0) (1,1) (0,1) (1,0)
+//   q=-1: (3,0) (3,1) (0,3) (1,3),
+// and the coefficients that turn the neighbour sums into the table index.
+// The frozen states (|q| = 2) get one null move with index of (0, 0, 0).
+void build_transition_table(std::vector<uint32_t> &trans)
+{
+    static const int kS[4] = {0, 0, 1, -1}, kG[4] = {1, -1, 0, 0};
+    static const int kPlus1[4][2] = {{2, 0}, {2, 1}, {0, 2}, {1, 2}};
+    static const int kZero[6][2] = {{2, 3}, {3, 2}, {0, 0}, {1, 1}, {0, 1}, {1, 0}};
+    static const int kMinus1[4][2] = {{3, 0}, {3, 1}, {0, 3}, {1, 3}};
+    trans.assign(2 * (size_t)kTransEntries, 0u);
+    const int center = 1 * (kTabV * kTabJ) + 16 * kTabJ + 16;
+    for (int st = 0; st < 16; ++st) {
+        const int ca = st & 3, cb = st >> 2, q = kS[ca] + kS[cb];
+        const int (*set)[2] = q == 1 ? kPlus1 : (q == 0 ? kZero : (q == -1 ? kMinus1 : nullptr));
+        const int kq = set ? (q == 0 ? 6 : 4) : 1;
+        for (int j = 0; j < kq; ++j) {
+            const int a1 = set ? set[j][0] : ca, b1 = set ? set[j][1] : cb;
+            const int dSa = kS[a1] - kS[ca], dSb = kS[b1] - kS[cb];
+            const int dGa = kG[a1] - kG[ca], dGb = kG[b1] - kG[cb];
+            const int nD = kS[a1] * kS[a1] + kS[b1] * kS[b1] - kS[ca] * kS[ca] - kS[cb] * kS[cb];
+            // idx = (nD/2+1)*1089 + (nV+16)*33 + (nJ+16); with the +4 offsets of the
+            // packed sums, 33*(dSa*4 + dSb*4) vanishes (dSa + dSb = 0) and
+            // dGa*4 + dGb*4 is subtracted here.
+            const int C = center + (nD / 2) * (kTabV * kTabJ) - 4 * (dGa + dGb);
+            const uint32_t coef = (uint32_t)(uint8_t)(int8_t)(33 * dSa) | ((uint32_t)(uint8_t)(int8_t)(33 * dSb) << 8) |
+                                  ((uint32_t)(uint8_t)(int8_t)dGa << 16) | ((uint32_t)(uint8_t)(int8_t)dGb << 24);
+            const uint32_t meta = (uint32_t)C | ((uint32_t)(a1 | (b1 << 2)) << 16);
+            trans[2 * (size_t)(st * 6 + j)] = coef;
+            trans[2 * (size_t)(st * 6 + j) + 1] = meta;
+        }
+    }
+}
+
+Tuning2Bit tuning_from_env()
+{
+    Tuning2Bit t{0, 0};
+    if (const char *v = std::getenv("LATTICE_2BIT_ROWS")) t.rows_per_block = std::atoi(v);
+    if (const char *v = std::getenv("LATTICE_2BIT_BLOCKS_PER_CU")) t.blocks_per_cu = std::atoi(v);
+    return t;
+}
+
 // Canonical row-major codes <-> device encoding.
 void to_device_layout(int32_t L, int32_t enc, const std::vector<int8_t> &codes, std::vector<uint8_t> &out)
 {
@@ -207,7 +272,8 @@ int enqueue_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
 {
     PhaseArgs a{};
     a.state = h->d_state;
-    a.thr = (const uint32_t *)(h->d_scratch + kScrTable);
+    a.dev_tab = (const uint2 *)(h->d_scratch + kScrDevTab);
+    a.trans = (const uint2 *)(h->d_scratch + kScrTrans);
     a.track = (unsigned long long *)(h->d_scratch + kScrTrack);
     a.L = h->L;
     a.key0 = (uint32_t)h->seed;
@@ -223,7 +289,7 @@ int enqueue_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
             a.m = sc.m[p];
             a.k = sc.k[p];
             const hipError_t e =
-                h->enc == LAT_ENC_INT8 ? launch_phase_int8(a, stream) : launch_phase_2bit(a, stream);
+                h->enc == LAT_ENC_INT8 ? launch_phase_int8(a, stream) : launch_phase_2bit(a, h->tuning, stream);
             if (e != hipSuccess) return hip_fail(e, "phase kernel launch");
         }
     }
@@ -290,8 +356,10 @@ int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void 
     }
     std::vector<uint8_t> dev;
     to_device_layout(p->L, p->encoding, codes, dev);
-    std::vector<uint32_t> tab;
+    std::vector<uint32_t> tab, dev_tab, trans;
     build_threshold_table(p->Delta, p->V, p->J, p->T, tab);
+    build_device_table(tab, dev_tab);
+    build_transition_table(trans);
 
     lattice *h = new lattice();
     h->L = p->L;
@@ -309,11 +377,15 @@ int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void 
     h->d_state = d_state;
     h->d_scratch = (uint8_t *)d_scratch;
     h->stream = (hipStream_t)hip_stream;
+    h->tuning = tuning_from_env();
     h->magic = kMagic;
 
     hipError_t e = hipMemcpyAsync(d_state, dev.data(), dev.size(), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(h->d_scratch + kScrTable, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, h->stream);
+        e = hipMemcpyAsync(h->d_scratch + kScrDevTab, dev_tab.data(), dev_tab.size() * 4, hipMemcpyHostToDevice,
+                           h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->d_scratch + kScrTrans, trans.data(), trans.size() * 4, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = launch_zero_i64((unsigned long long *)(h->d_scratch + kScrTrack), 10, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // host staging buffers die with this frame
     if (e != hipSuccess) {
