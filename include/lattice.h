@@ -126,9 +126,21 @@ int lattice_read_state(lattice *h, int8_t *host_codes);
 
 /* Advance `count` lattices by `sweeps` sweeps each, on hip_stream (section
  * 3.2: several lattice copies processed together).  Lattices may differ in
- * L, parameters and seed; results are identical to calling lattice_sweep on
- * each.  Errors: LAT_EINVAL, LAT_ESTATE, LAT_EHIP. */
+ * L, encoding, parameters and seed; results are identical to calling
+ * lattice_sweep on each.  Lattices with L <= 512 advance together in one
+ * launch per 256 of them, each resident in on-chip memory for all the sweeps;
+ * larger ones are advanced one after another.  The caller orders hip_stream
+ * after any pending work of the lattices' own streams.  A lattice may appear
+ * only once.  Errors: LAT_EINVAL, LAT_ESTATE, LAT_EHIP. */
 int lattice_sweep_batch(lattice *const *hs, int32_t count, uint32_t sweeps, void *hip_stream);
+
+/* Observables of `count` lattices (as lattice_observables) with one reduction
+ * launch per 256 lattices and one device-to-host copy.  d_out is caller-owned
+ * device scratch of at least 80*count bytes; out receives `count` records.
+ * Synchronises hip_stream.  Errors: LAT_EINVAL, LAT_ENOMEM, LAT_ESTATE,
+ * LAT_EHIP. */
+int lattice_observables_batch(lattice *const *hs, int32_t count, void *d_out, size_t out_bytes, lat_obs *out,
+                              void *hip_stream);
 
 /* Release the handle (host memory only; caller buffers are untouched). */
 int lattice_destroy(lattice *h);

@@ -27,6 +27,7 @@ EXPORTS = (
     "lattice_observables",
     "lattice_read_state",
     "lattice_sweep_batch",
+    "lattice_observables_batch",
     "lattice_destroy",
     "lattice_last_error",
 )
@@ -106,6 +107,8 @@ def lib() -> ctypes.CDLL:
         L.lattice_read_state.restype = ctypes.c_int
         L.lattice_sweep_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_uint32, vp]
         L.lattice_sweep_batch.restype = ctypes.c_int
+        L.lattice_observables_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, vp, sz, ctypes.POINTER(LatObs), vp]
+        L.lattice_observables_batch.restype = ctypes.c_int
         L.lattice_destroy.argtypes = [vp]
         L.lattice_destroy.restype = ctypes.c_int
         L.lattice_last_error.argtypes = []
@@ -206,7 +209,29 @@ class Lattice:
             pass
 
 
+def _handles(lattices):
+    return (ctypes.c_void_p * len(lattices))(*[lat.handle.value for lat in lattices])
+
+
 def sweep_batch(lattices, sweeps: int, stream=None):
     """Advance several lattices by `sweeps` sweeps each in one call."""
-    arr = (ctypes.c_void_p * len(lattices))(*[lat.handle.value for lat in lattices])
-    _check(lib().lattice_sweep_batch(arr, len(lattices), sweeps, _stream_handle(stream)))
+    _check(lib().lattice_sweep_batch(_handles(lattices), len(lattices), sweeps, _stream_handle(stream)))
+
+
+class BatchObservables:
+    """Reusable device output buffer for observables_batch()."""
+
+    def __init__(self, capacity: int, device: str = "cuda"):
+        import torch
+
+        self.capacity = capacity
+        self.buf = torch.empty(80 * max(1, capacity), dtype=torch.uint8, device=device)
+
+    def __call__(self, lattices, stream=None) -> list:
+        n = len(lattices)
+        if n > self.capacity:
+            raise ValueError("more lattices than the buffer holds")
+        out = (LatObs * max(1, n))()
+        _check(lib().lattice_observables_batch(_handles(lattices), n, self.buf.data_ptr(), self.buf.numel(), out,
+                                               _stream_handle(stream)))
+        return list(out)[:n]

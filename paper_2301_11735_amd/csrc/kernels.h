@@ -12,26 +12,56 @@ namespace lat {
 constexpr int kTabV = 33, kTabJ = 33;
 constexpr int kTabSize = 5 * kTabV * kTabJ;  // 5445
 
-// Device form of the threshold table.  A pair move changes the charged count
-// by 0 or +-2, so only the slices nD in {-2, 0, 2} are reachable; entry
-// (nD/2+1)*1089 + (nV+16)*33 + (nJ+16) holds {threshold, packed triple}
-// where packed = 1<<27 | (nD+2)<<20 | (nV+16)<<10 | (nJ+16) is what an
-// accepted move adds to the per-thread energy tracker.
-constexpr int kDevTabEntries = 3 * kTabV * kTabJ;  // 3267 x uint2
+// Device form of the threshold table, compacted to the triples a pair move
+// can reach: a move that changes the charged count (nD = +-2) or a q = +-1
+// move has |nV|, |nJ| <= 8; a charge swap (+,-) <-> (-,+) has nD = nJ = 0 and
+// |nV| <= 16; a spin change of both-spin or one-spin pairs has nD = nV = 0
+// and |nJ| <= 16.  Regions (entries {threshold, packed triple}):
+//   slice s = nD/2 + 1:  289*s + (nV+8)*17 + (nJ+8)     |nV|, |nJ| <= 8
+//   V line (nD = nJ = 0): kDevVLine + nV + 16
+//   J line (nD = nV = 0): kDevJLine + nJ + 16
+// packed = 1<<27 | (nD+2)<<20 | (nV+16)<<10 | (nJ+16) is what an accepted
+// move adds to the per-thread energy tracker.
+constexpr int kDevSlice = 17 * 17;
+constexpr int kDevVLine = 3 * kDevSlice;       // 867
+constexpr int kDevJLine = kDevVLine + 33;      // 900
+constexpr int kDevTabEntries = kDevJLine + 33; // 933 x uint2
 // Transition table: entry st*6 + j for pair state st = code_a | code_b<<2 and
-// choice j: {coef, meta}.  coef = int8x4 (33*dS_a, 33*dS_b, dsig_a, dsig_b);
-// meta = C | new_state<<16, with C chosen so that
-// dot4(coef, (sumS_a+4, sumS_b+4, sumsig_a+4, sumsig_b+4)) + C is the
-// device-table index of the move's (nD, nV, nJ).
+// choice j: {coef, meta}.  coef = int8x4 applied to the packed neighbour sums
+// (sumS_a+4, sumS_b+4, sumsig_a+4, sumsig_b+4); meta = C | new_state<<16, with
+// C chosen so that dot4(coef, sums) + C is the move's device-table index.
 constexpr int kTransEntries = 16 * 6;
 
 // Scratch buffer layout (bytes).  Tracker (3 int64) and observable sums
 // (7 int64) are adjacent so one 80-byte copy returns both.
-constexpr size_t kScrDevTab = 0;                      // 3267 x 8 = 26136
-constexpr size_t kScrTrans = 26368;                   // 96 x 8 = 768
-constexpr size_t kScrTrack = 27136;                   // 3 x int64
+constexpr size_t kScrDevTab = 0;                      // 933 x 8 = 7464
+constexpr size_t kScrTrans = 7680;                    // 96 x 8 = 768
+constexpr size_t kScrTrack = 8448;                    // 3 x int64
 constexpr size_t kScrObs = kScrTrack + 3 * 8;         // 7 x int64
-constexpr size_t kScrBytes = 32768;
+constexpr size_t kScrDesc = 8704;                     // LatDesc
+constexpr size_t kScrBytes = 16384;
+
+// Per-lattice descriptor kept in the lattice's scratch, read by the batched
+// kernel.  next_sweep is advanced on the device by every path that sweeps.
+struct LatDesc {
+    void *state;
+    int32_t L, enc;
+    uint32_t key0, key1;
+    uint64_t next_sweep;
+};
+
+// Lattices whose whole state fits one block's LDS run in the batched kernel:
+// 8 sublattice classes of (L/2) rows x ceil(L/64) words (2 bits per site).
+constexpr int kLdsMaxL = 512;
+inline size_t lds_state_words(int L) { return (size_t)8 * (L / 2) * ((L / 4 + 15) / 16); }
+
+// One launch of the batched kernel: block b advances lattice b by `sweeps`.
+constexpr int kMaxBatch = 256;
+struct BatchArgs {
+    int count;
+    uint32_t sweeps;
+    uint8_t *scratch[kMaxBatch];
+};
 
 // One phase of one sweep: phase p, displacement D = (r + 4m, 1 + 2k).
 struct PhaseArgs {
@@ -50,11 +80,19 @@ struct PhaseArgs {
 struct Tuning2Bit {
     int rows_per_block;
     int blocks_per_cu;
+    int waves_hint;  // >= 8: the build limited to 64 VGPRs (8 waves per SIMD)
 };
 
 hipError_t launch_phase_int8(const PhaseArgs &a, hipStream_t s);
 hipError_t launch_phase_2bit(const PhaseArgs &a, const Tuning2Bit &t, hipStream_t s);
 hipError_t launch_zero_i64(unsigned long long *p, int n, hipStream_t s);
 hipError_t launch_observables(const void *state, int L, int encoding, unsigned long long *obs, hipStream_t s);
+// Batched kernel; block size and dynamic LDS are sized for the largest L.
+hipError_t launch_sweep_lds(const BatchArgs &a, int max_L, hipStream_t s);
+// desc->next_sweep += sweeps (after host-scheduled phase launches).
+hipError_t launch_advance(LatDesc *desc, uint32_t sweeps, hipStream_t s);
+// Observables of `count` lattices in one launch: out[10*b .. 10*b+9] =
+// (tracker nD, nV, nJ, then the 7 sums) of lattice b.
+hipError_t launch_observables_batch(const BatchArgs &a, unsigned long long *out, hipStream_t s);
 
 }  // namespace lat

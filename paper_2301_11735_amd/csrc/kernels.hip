@@ -170,12 +170,13 @@ __global__ void __launch_bounds__(256) k_phase_int8(PhaseArgs a)
 // after the block barrier, thread j assembles b-word jb+1 from its own new
 // codes and those of thread j+1 (mod W), and every b-word has one writer.
 
-// 16 sites of a class row starting at class position xs (periodic).
-__device__ __forceinline__ uint32_t load16(const uint32_t *__restrict__ row, int W, int xs)
+// 16 sites of the class row at word offset `row` of `st`, starting at class
+// position xs (periodic).  32-bit offsets keep the base pointer uniform.
+__device__ __forceinline__ uint32_t load16(const uint32_t *__restrict__ st, uint32_t row, int W, int xs)
 {
     const int jw = xs >> 4, sh = xs & 15;
-    const uint32_t w0 = row[jw];
-    const uint32_t w1 = row[jw + 1 == W ? 0 : jw + 1];
+    const uint32_t w0 = st[row + (uint32_t)jw];
+    const uint32_t w1 = st[row + (uint32_t)(jw + 1 == W ? 0 : jw + 1)];
     return sh ? __builtin_amdgcn_alignbit(w1, w0, 2u * (uint32_t)sh) : w0;
 }
 
@@ -217,18 +218,27 @@ __device__ __forceinline__ void transpose4(uint32_t r0, uint32_t r1, uint32_t r2
     c3 = __builtin_amdgcn_perm(p23hi, p01hi, 0x07060302u);
 }
 
-__global__ void __launch_bounds__(1024) k_phase_2bit(PhaseArgs a, int rows_per_block)
+// MinWaves > 1 asks the compiler to fit MinWaves waves per SIMD (at most
+// 512/MinWaves VGPRs), e.g. two 1024-thread blocks per compute unit at 8.
+// The ten words one thread reads for its 16 pairs: its a-word, the a-words'
+// left/right/up/down neighbour words, and the same five for the 16 partners
+// (the b-side words start mid-word and are funnel-shifted into place).
+struct PairWords {
+    uint32_t A0, AL, AR, AU, AD, B0, BL, BR, BU, BD;
+};
+
+template <int MinWaves>
+__global__ void __launch_bounds__(1024, MinWaves) k_phase_2bit(PhaseArgs a, int rows_per_block)
 {
     __shared__ uint2 s_tab[kDevTabEntries];
     __shared__ uint2 s_trans[kTransEntries];
     extern __shared__ uint32_t xch[];  // 2 x blockDim (double buffered)
-    stage_tables(s_tab, s_trans, a.dev_tab, a.trans);
 
     const int L = a.L, W = L >> 6, H = L >> 1, Lq = L >> 2;
     const int rr = threadIdx.x / W, j = threadIdx.x - rr * W;
     const int n_groups = H / rows_per_block;
     uint32_t *st = (uint32_t *)a.state;
-    const size_t csz = (size_t)H * W;
+    const uint32_t csz = (uint32_t)H * (uint32_t)W;  // words per class; N/16 < 2^32
     const int p = a.p;
     const int pb = (p + a.r) & 3, carry = (p + a.r) >> 2;
     int dX = a.m + carry;
@@ -236,74 +246,105 @@ __global__ void __launch_bounds__(1024) k_phase_2bit(PhaseArgs a, int rows_per_b
     int Xb = 16 * j + dX;
     if (Xb >= Lq) Xb -= Lq;
     const int jb = Xb >> 4, shb = Xb & 15;
-    const int jw_out = jb + 1 == W ? 0 : jb + 1;
+    const uint32_t jw_out = (uint32_t)(jb + 1 == W ? 0 : jb + 1);
     const int j_next = j + 1 == W ? 0 : j + 1;
-    // class rows of the a side and the b side (row offsets added per group)
-    uint32_t *cA0 = st + (size_t)p * csz;
-    const uint32_t *cAL = p > 0 ? st + (size_t)(p - 1) * csz : st + 3 * csz;
-    const uint32_t *cAR = p < 3 ? st + (size_t)(p + 1) * csz : st;
-    const uint32_t *cAV = st + (size_t)(4 + p) * csz;
-    uint32_t *cB0 = st + (size_t)(4 + pb) * csz;
-    const uint32_t *cBL = pb > 0 ? st + (size_t)(4 + pb - 1) * csz : st + 7 * csz;
-    const uint32_t *cBR = pb < 3 ? st + (size_t)(4 + pb + 1) * csz : st + 4 * csz;
-    const uint32_t *cBV = st + (size_t)pb * csz;
+    // word offsets of the classes read on the a side and the b side
+    const uint32_t oA0 = (uint32_t)p * csz;
+    const uint32_t oAL = (uint32_t)(p > 0 ? p - 1 : 3) * csz;
+    const uint32_t oAR = (uint32_t)(p < 3 ? p + 1 : 0) * csz;
+    const uint32_t oAV = (uint32_t)(4 + p) * csz;
+    const uint32_t oB0 = (uint32_t)(4 + pb) * csz;
+    const uint32_t oBL = (uint32_t)(pb > 0 ? 4 + pb - 1 : 7) * csz;
+    const uint32_t oBR = (uint32_t)(pb < 3 ? 4 + pb + 1 : 4) * csz;
+    const uint32_t oBV = (uint32_t)pb * csz;
     const int xAL = p > 0 ? 16 * j : (j == 0 ? Lq - 1 : 16 * j - 1);
     const int xAR = p < 3 ? 16 * j : 16 * j + 1;
     const int xBL = pb > 0 ? Xb : (Xb == 0 ? Lq - 1 : Xb - 1);
     const int xBR = pb < 3 ? Xb : (Xb + 1 == Lq ? 0 : Xb + 1);
 
+    auto row_of = [&](int g) { return g * rows_per_block + rr; };
+    auto brow_of = [&](int Y) { return Y + a.k >= H ? Y + a.k - H : Y + a.k; };
+    auto load_words = [&](int g) {
+        const int Y = row_of(g), Yb = brow_of(Y);
+        const uint32_t ro = (uint32_t)Y * W, rob = (uint32_t)Yb * W;
+        const uint32_t roU = (uint32_t)(Y == 0 ? H - 1 : Y - 1) * W;
+        const uint32_t robD = (uint32_t)(Yb + 1 == H ? 0 : Yb + 1) * W;
+        PairWords w;
+        w.A0 = st[oA0 + ro + j];
+        w.AL = load16(st, oAL + ro, W, xAL);
+        w.AR = load16(st, oAR + ro, W, xAR);
+        w.AU = st[oAV + roU + j];
+        w.AD = st[oAV + ro + j];
+        w.B0 = load16(st, oB0 + rob, W, Xb);
+        w.BL = load16(st, oBL + rob, W, xBL);
+        w.BR = load16(st, oBR + rob, W, xBR);
+        w.BU = load16(st, oBV + rob, W, Xb);
+        w.BD = load16(st, oBV + robD, W, Xb);
+        return w;
+    };
+
+    // The first group's words are in flight while the tables are staged; each
+    // later group's words are fetched before the current group is computed.
+    // Every word read is either never written in this phase or written only
+    // by this block in the iteration that owns it, after its read.
+    int g = blockIdx.x;
+    PairWords cur{};
+    if (g < n_groups) cur = load_words(g);
+    stage_tables(s_tab, s_trans, a.dev_tab, a.trans);
+
     int tr[3] = {0, 0, 0};
     int buf = 0;
-    for (int g = blockIdx.x; g < n_groups; g += gridDim.x, buf ^= 1) {
-        const int Y = g * rows_per_block + rr;
-        int Yb = Y + a.k;
-        if (Yb >= H) Yb -= H;
-        const size_t ro = (size_t)Y * W, rob = (size_t)Yb * W;
-        const uint32_t A0 = cA0[ro + j];
-        const uint32_t AL = load16(cAL + ro, W, xAL);
-        const uint32_t AR = load16(cAR + ro, W, xAR);
-        const uint32_t AU = cAV[(size_t)(Y == 0 ? H - 1 : Y - 1) * W + j];
-        const uint32_t AD = cAV[ro + j];
-        const uint32_t B0 = load16(cB0 + rob, W, Xb);
-        const uint32_t BL = load16(cBL + rob, W, xBL);
-        const uint32_t BR = load16(cBR + rob, W, xBR);
-        const uint32_t BU = load16(cBV + rob, W, Xb);
-        const uint32_t BD = load16(cBV + (size_t)(Yb + 1 == H ? 0 : Yb + 1) * W, W, Xb);
+    for (; g < n_groups; g += gridDim.x, buf ^= 1) {
+        const int gn = g + gridDim.x;
+        PairWords nxt{};
+        if (gn < n_groups) nxt = load_words(gn);
+        const int Y = row_of(g), Yb = brow_of(Y);
 
-        const SideSums sa = side_sums(AL, AR, AU, AD);
-        const SideSums sb = side_sums(BL, BR, BU, BD);
-        // bpack[t] = (sumS_a+4, sumS_b+4, sumsig_a+4, sumsig_b+4) of site t;
-        // group t&3 comes from one nibble plane, byte t>>2 within it.
-        uint32_t bp[16];
-        transpose4(sa.ES & kM0F, sb.ES & kM0F, sa.EG & kM0F, sb.EG & kM0F, bp[0], bp[4], bp[8], bp[12]);
-        transpose4(sa.OS & kM0F, sb.OS & kM0F, sa.OG & kM0F, sb.OG & kM0F, bp[1], bp[5], bp[9], bp[13]);
-        transpose4((sa.ES >> 4) & kM0F, (sb.ES >> 4) & kM0F, (sa.EG >> 4) & kM0F, (sb.EG >> 4) & kM0F, bp[2],
-                   bp[6], bp[10], bp[14]);
-        transpose4((sa.OS >> 4) & kM0F, (sb.OS >> 4) & kM0F, (sa.OG >> 4) & kM0F, (sb.OG >> 4) & kM0F, bp[3],
-                   bp[7], bp[11], bp[15]);
-
+        const SideSums sa = side_sums(cur.AL, cur.AR, cur.AU, cur.AD);
+        const SideSums sb = side_sums(cur.BL, cur.BR, cur.BU, cur.BD);
+        // bpack of site t = (sumS_a+4, sumS_b+4, sumsig_a+4, sumsig_b+4): site
+        // t = 4k + g is byte k of nibble plane g (g = 0, 2: even sites, low and
+        // high nibbles; g = 1, 3: odd sites).  Philox call c serves t = 2c and
+        // 2c+1, so calls 0,2,4,6 need planes 0 and 1, calls 1,3,5,7 planes 2
+        // and 3; handling them in that order keeps 8 packed words live.
         uint32_t Anew = 0u, Bnew = 0u, packed = 0u;
         const uint32_t call0 = (uint32_t)Y * (uint32_t)(Lq >> 1) + 8u * (uint32_t)j;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const u32x4 w = philox4x32_10(a.s_lo, (uint32_t)p, call0 + (uint32_t)c, a.s_hi, a.key0, a.key1);
+        for (int half = 0; half < 2; ++half) {
+            uint32_t ge[4], go[4];
+            const int sh = 4 * half;
+            transpose4((sa.ES >> sh) & kM0F, (sb.ES >> sh) & kM0F, (sa.EG >> sh) & kM0F, (sb.EG >> sh) & kM0F,
+                       ge[0], ge[1], ge[2], ge[3]);
+            transpose4((sa.OS >> sh) & kM0F, (sb.OS >> sh) & kM0F, (sa.OG >> sh) & kM0F, (sb.OG >> sh) & kM0F,
+                       go[0], go[1], go[2], go[3]);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int t = 2 * c + h;
-                const uint32_t s0 = ((A0 >> (2 * t)) & 3u) | (((B0 >> (2 * t)) & 3u) << 2);
-                const uint32_t ns = pair_step(s0, bp[t], h ? w.z : w.x, h ? w.w : w.y, s_trans, s_tab, packed);
-                Anew |= (ns & 3u) << (2 * t);
-                Bnew |= (ns >> 2) << (2 * t);
+            for (int k = 0; k < 4; ++k) {
+                const int c = 2 * k + half;
+                const u32x4 w =
+                    philox4x32_10(a.s_lo, (uint32_t)p, call0 + (uint32_t)c, a.s_hi, a.key0, a.key1);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int t = 2 * c + h;
+                    const uint32_t s0 = ((cur.A0 >> (2 * t)) & 3u) | (((cur.B0 >> (2 * t)) & 3u) << 2);
+                    const uint32_t ns = pair_step(s0, h ? go[k] : ge[k], h ? w.z : w.x, h ? w.w : w.y, s_trans,
+                                                  s_tab, packed);
+                    Anew |= (ns & 3u) << (2 * t);
+                    Bnew |= (ns >> 2) << (2 * t);
+                }
+                // keep the scheduler from hoisting every Philox call at once
+                // (register pressure decides how many waves fit per SIMD)
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         unpack_tracker(packed, tr);
-        cA0[ro + j] = Anew;
+        st[oA0 + (uint32_t)Y * W + j] = Anew;
         uint32_t *x = xch + buf * blockDim.x;
         x[threadIdx.x] = Bnew;
         __syncthreads();
-        const uint32_t nxt = x[rr * W + j_next];
-        const uint32_t word = shb ? __builtin_amdgcn_alignbit(nxt, Bnew, 32u - 2u * (uint32_t)shb) : nxt;
-        cB0[rob + jw_out] = word;
+        const uint32_t nb = x[rr * W + j_next];
+        const uint32_t word = shb ? __builtin_amdgcn_alignbit(nb, Bnew, 32u - 2u * (uint32_t)shb) : nb;
+        st[oB0 + (uint32_t)Yb * W + jw_out] = word;
+        cur = nxt;
     }
     block_reduce_add<3>(tr, a.track);
 }
@@ -366,7 +407,7 @@ __global__ void __launch_bounds__(256) k_obs_2bit(const uint32_t *__restrict__ s
         const int cx = c & 3, cy = c >> 2;
         const uint32_t w = st[i];
         const uint32_t wr = cx < 3 ? st[i + csz]
-                                   : load16(st + (size_t)(4 * cy) * csz + (size_t)Y * W, W,
+                                   : load16(st, (uint32_t)((size_t)(4 * cy) * csz + (size_t)Y * W), W,
                                             16 * j + 1 == Lq ? 0 : 16 * j + 1);
         const uint32_t wd = cy == 0 ? st[i + 4 * csz]
                                     : st[(size_t)cx * csz + (size_t)(Y + 1 == H ? 0 : Y + 1) * W + j];
@@ -386,6 +427,219 @@ __global__ void __launch_bounds__(256) k_obs_2bit(const uint32_t *__restrict__ s
         v[6] += sg * sumS;
     }
     block_reduce_add<7>(v, obs);
+}
+
+// ---------------------------------------------------------------------------
+// Batched lattices (section 3.2: several lattice copies processed together),
+// one block per lattice, the whole lattice resident in LDS for all sweeps of
+// the launch.  LDS layout: the 8 sublattice classes, each (L/2) rows of
+// Wp = ceil(L/64) words, site X of a class row at bits 2*(X&15) of word X>>4.
+// Each thread owns Philox calls t = tid, tid + blockDim, ...: pairs 2t and
+// 2t+1.  A pair's two sites are in words other pairs of the phase also own
+// fields of, so the new codes are merged with LDS atomic xor; every read of
+// an updated word extracts only the reader's own field, which nobody else
+// writes, and neighbour words are never written in the phase.
+
+// Schedule of sweep s (same definition as the host's): r in {1,2,3};
+// phase p has D_p = (r + 4 m_p, 1 + 2 k_p).
+__device__ __forceinline__ void device_schedule(int L, uint32_t k0, uint32_t k1, uint64_t s, int &r, int (&m)[4],
+                                                int (&k)[4])
+{
+    uint32_t Wd[12];
+#pragma unroll
+    for (uint32_t t = 0; t < 3; ++t) {
+        const u32x4 w = philox4x32_10((uint32_t)s, kDomSchedule, t, (uint32_t)(s >> 32), k0, k1);
+        Wd[4 * t] = w.x;
+        Wd[4 * t + 1] = w.y;
+        Wd[4 * t + 2] = w.z;
+        Wd[4 * t + 3] = w.w;
+    }
+    r = 1 + (int)(((Wd[0] >> 8) * 3u) >> 24);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        m[p] = (int)mulhi_u32(Wd[1 + 2 * p], (uint32_t)(L / 4));
+        k[p] = (int)mulhi_u32(Wd[2 + 2 * p], (uint32_t)(L / 2));
+    }
+}
+
+struct LdsGeom {
+    int L, Lq, H, Wp;
+    uint32_t csz;  // words per class
+    __device__ __forceinline__ uint32_t word(int c, int Y, int X) const
+    {
+        return (uint32_t)c * csz + (uint32_t)Y * Wp + (uint32_t)(X >> 4);
+    }
+};
+
+__device__ __forceinline__ uint32_t lds_code(const uint32_t *lat, const LdsGeom &g, int c, int Y, int X)
+{
+    return (lat[g.word(c, Y, X)] >> (2 * (X & 15))) & 3u;
+}
+
+__global__ void __launch_bounds__(1024) k_sweep_lds(BatchArgs args)
+{
+    __shared__ uint2 s_tab[kDevTabEntries];
+    __shared__ uint2 s_trans[kTransEntries];
+    extern __shared__ uint32_t lat[];
+    uint8_t *scr = args.scratch[blockIdx.x];
+    const LatDesc d = *(const LatDesc *)(scr + kScrDesc);
+    stage_tables(s_tab, s_trans, (const uint2 *)(scr + kScrDevTab), (const uint2 *)(scr + kScrTrans));
+    LdsGeom g;
+    g.L = d.L;
+    g.Lq = d.L >> 2;
+    g.H = d.L >> 1;
+    g.Wp = (g.Lq + 15) >> 4;
+    g.csz = (uint32_t)g.H * g.Wp;
+    const int L = g.L, Lq = g.Lq, H = g.H;
+    const uint32_t nwords = 8u * g.csz;
+
+    // global -> LDS
+    if (d.enc == 1) {
+        const uint32_t *src = (const uint32_t *)d.state;  // same layout, Wp = L/64
+        for (uint32_t i = threadIdx.x; i < nwords; i += blockDim.x) lat[i] = src[i];
+    } else {
+        const int8_t *src = (const int8_t *)d.state;
+        for (uint32_t i = threadIdx.x; i < nwords; i += blockDim.x) {
+            const int c = (int)(i / g.csz);
+            const uint32_t rem = i - (uint32_t)c * g.csz;
+            const int Y = (int)(rem / g.Wp), w = (int)(rem - (uint32_t)Y * g.Wp);
+            const int x0 = c & 3, y = 2 * Y + (c >> 2);
+            uint32_t v = 0;
+            for (int t = 0; t < 16; ++t) {
+                const int X = 16 * w + t;
+                if (X < Lq) v |= ((uint32_t)src[(size_t)y * L + 4 * X + x0] & 3u) << (2 * t);
+            }
+            lat[i] = v;
+        }
+    }
+    __syncthreads();
+
+    const uint32_t n_calls = (uint32_t)L * (uint32_t)L / 16u;
+    int tr[3] = {0, 0, 0};
+    for (uint64_t s = d.next_sweep; s < d.next_sweep + args.sweeps; ++s) {
+        int r, mm[4], kk[4];
+        device_schedule(L, d.key0, d.key1, s, r, mm, kk);
+        for (int p = 0; p < 4; ++p) {
+            const int pb = (p + r) & 3, carry = (p + r) >> 2;
+            int dX = mm[p] + carry;
+            if (dX >= Lq) dX -= Lq;
+            const int cAL = p > 0 ? p - 1 : 3, cAR = p < 3 ? p + 1 : 0;
+            const int cBL = pb > 0 ? 4 + pb - 1 : 7, cBR = pb < 3 ? 4 + pb + 1 : 4;
+            for (uint32_t t = threadIdx.x; t < n_calls; t += blockDim.x) {
+                const u32x4 w = philox4x32_10((uint32_t)s, (uint32_t)p, t, (uint32_t)(s >> 32), d.key0, d.key1);
+                uint32_t packed = 0;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const uint32_t pi = 2u * t + (uint32_t)h;
+                    const int Y = (int)(pi / (uint32_t)Lq), X = (int)pi - Y * Lq;
+                    int Yb = Y + kk[p], Xb = X + dX;
+                    if (Yb >= H) Yb -= H;
+                    if (Xb >= Lq) Xb -= Lq;
+                    const int Xl = X == 0 ? Lq - 1 : X - 1, Xr = X + 1 == Lq ? 0 : X + 1;
+                    const int Xbl = Xb == 0 ? Lq - 1 : Xb - 1, Xbr = Xb + 1 == Lq ? 0 : Xb + 1;
+                    const uint32_t ca = lds_code(lat, g, p, Y, X);
+                    const uint32_t cb = lds_code(lat, g, 4 + pb, Yb, Xb);
+                    const uint32_t bpack =
+                        contrib_a(lds_code(lat, g, cAL, Y, p > 0 ? X : Xl)) +
+                        contrib_a(lds_code(lat, g, cAR, Y, p < 3 ? X : Xr)) +
+                        contrib_a(lds_code(lat, g, 4 + p, Y == 0 ? H - 1 : Y - 1, X)) +
+                        contrib_a(lds_code(lat, g, 4 + p, Y, X)) +
+                        contrib_b(lds_code(lat, g, cBL, Yb, pb > 0 ? Xb : Xbl)) +
+                        contrib_b(lds_code(lat, g, cBR, Yb, pb < 3 ? Xb : Xbr)) +
+                        contrib_b(lds_code(lat, g, pb, Yb, Xb)) +
+                        contrib_b(lds_code(lat, g, pb, Yb + 1 == H ? 0 : Yb + 1, Xb));
+                    const uint32_t s0 = ca | (cb << 2);
+                    const uint32_t ns = pair_step(s0, bpack, h ? w.z : w.x, h ? w.w : w.y, s_trans, s_tab, packed);
+                    if (ns != s0) {
+                        atomicXor(&lat[g.word(p, Y, X)], ((ns ^ s0) & 3u) << (2 * (X & 15)));
+                        atomicXor(&lat[g.word(4 + pb, Yb, Xb)], ((ns ^ s0) >> 2) << (2 * (Xb & 15)));
+                    }
+                }
+                unpack_tracker(packed, tr);
+            }
+            __syncthreads();
+        }
+    }
+
+    // LDS -> global
+    if (d.enc == 1) {
+        uint32_t *dst = (uint32_t *)d.state;
+        for (uint32_t i = threadIdx.x; i < nwords; i += blockDim.x) dst[i] = lat[i];
+    } else {
+        int8_t *dst = (int8_t *)d.state;
+        for (uint32_t i = threadIdx.x; i < (uint32_t)L * L; i += blockDim.x) {
+            const int y = (int)(i / L), x = (int)(i - (uint32_t)y * L);
+            dst[i] = (int8_t)lds_code(lat, g, 4 * (y & 1) + (x & 3), y >> 1, x >> 2);
+        }
+    }
+    if (threadIdx.x == 0) ((LatDesc *)(scr + kScrDesc))->next_sweep = d.next_sweep + args.sweeps;
+    block_reduce_add<3>(tr, (unsigned long long *)(scr + kScrTrack));
+}
+
+__global__ void k_advance(LatDesc *desc, uint32_t sweeps)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) desc->next_sweep += sweeps;
+}
+
+// Observables of many lattices from their global state: block b reduces
+// lattice b and writes (tracker, 7 sums) to out[10b ..].
+__global__ void __launch_bounds__(256) k_obs_batch(BatchArgs args, unsigned long long *out)
+{
+    uint8_t *scr = args.scratch[blockIdx.x];
+    const LatDesc d = *(const LatDesc *)(scr + kScrDesc);
+    const int L = d.L;
+    long long v[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (d.enc == 0) {
+        const int8_t *st = (const int8_t *)d.state;
+        for (uint32_t i = threadIdx.x; i < (uint32_t)L * L; i += blockDim.x) {
+            const int y = (int)(i / L), x = (int)(i - (uint32_t)y * L);
+            const uint32_t c = (uint32_t)st[i];
+            const uint32_t cr = (uint32_t)st[(size_t)y * L + (x + 1 == L ? 0 : x + 1)];
+            const uint32_t cd = (uint32_t)st[(size_t)(y + 1 == L ? 0 : y + 1) * L + x];
+            const int S = charge_of(c), G = spin_of(c), sg = ((x + y) & 1) ? -1 : 1;
+            v[0] += S;
+            v[1] += S * S;
+            v[2] += S * (charge_of(cr) + charge_of(cd));
+            v[3] += G * (spin_of(cr) + spin_of(cd));
+            v[4] += G;
+            v[5] += sg * G;
+            v[6] += sg * S;
+        }
+    } else {
+        const uint32_t *st = (const uint32_t *)d.state;
+        const int W = L >> 6, H = L >> 1, Lq = L >> 2;
+        const uint32_t csz = (uint32_t)H * W;
+        for (uint32_t i = threadIdx.x; i < 8u * csz; i += blockDim.x) {
+            const int c = (int)(i / csz);
+            const uint32_t rem = i - (uint32_t)c * csz;
+            const int Y = (int)(rem / W), j = (int)(rem - (uint32_t)Y * W);
+            const int cx = c & 3, cy = c >> 2;
+            const uint32_t w = st[i];
+            const uint32_t wr = cx < 3 ? st[i + csz]
+                                       : load16(st, (uint32_t)(4 * cy) * csz + (uint32_t)Y * W, W,
+                                                16 * j + 1 == Lq ? 0 : 16 * j + 1);
+            const uint32_t wd = cy == 0 ? st[i + 4 * csz] : st[(uint32_t)cx * csz + (uint32_t)(Y + 1 == H ? 0 : Y + 1) * W + j];
+            const uint32_t h = (w >> 1) & kM5, l = w & kM5;
+            const int sumS = __popc(h & ~l) - __popc(h & l);
+            const int sumG = __popc((h | l) ^ kM5) - __popc(l & ~h);
+            int bSS = 0, bss = 0;
+            bond_sums(h, l, (wr >> 1) & kM5, wr & kM5, bSS, bss);
+            bond_sums(h, l, (wd >> 1) & kM5, wd & kM5, bSS, bss);
+            const int sg = ((cx + cy) & 1) ? -1 : 1;
+            v[0] += sumS;
+            v[1] += __popc(h);
+            v[2] += bSS;
+            v[3] += bss;
+            v[4] += sumG;
+            v[5] += sg * sumG;
+            v[6] += sg * sumS;
+        }
+    }
+    unsigned long long *o = out + 10 * (size_t)blockIdx.x;
+    if (threadIdx.x < 10) o[threadIdx.x] = 0ull;
+    __syncthreads();
+    block_reduce_add<7>(v, o + 3);
+    if (threadIdx.x < 3) o[threadIdx.x] = ((const unsigned long long *)(scr + kScrTrack))[threadIdx.x];
 }
 
 int g_num_cus = 0;
@@ -418,16 +672,14 @@ hipError_t launch_phase_int8(const PhaseArgs &a, hipStream_t s)
 }
 
 // Rows per block: a power of two <= 32 (so it divides the L/2 = 32W rows);
-// by default the largest giving at most 256 threads.  Every block holds
-// whole class rows.
+// by default the largest giving at most 1024 threads.  Every block holds
+// whole class rows.  One such block per compute unit stages the LDS tables
+// once per launch and was the fastest shape measured at L = 8192.
 static int rows_per_block_2bit(int W, int requested)
 {
+    const int cap = requested > 0 ? requested : 32;
     int r = 1;
-    if (requested > 0) {
-        while (r < 32 && 2 * r <= requested && 2 * r * W <= 1024) r *= 2;
-        return r;
-    }
-    while (r < 32 && 2 * r * W <= 256) r *= 2;
+    while (r < 32 && 2 * r <= cap && 2 * r * W <= 1024) r *= 2;
     return r;
 }
 
@@ -437,9 +689,12 @@ hipError_t launch_phase_2bit(const PhaseArgs &a, const Tuning2Bit &t, hipStream_
     const int R = rows_per_block_2bit(W, t.rows_per_block);
     const int block = R * W;
     int grid = H / R;
-    const int bpc = t.blocks_per_cu > 0 ? t.blocks_per_cu : 4;
+    const int bpc = t.blocks_per_cu > 0 ? t.blocks_per_cu : 1;
     if (grid > bpc * num_cus()) grid = bpc * num_cus();
-    hipLaunchKernelGGL(k_phase_2bit, dim3(grid), dim3(block), (size_t)block * 8u, s, a, R);
+    if (t.waves_hint >= 8)
+        hipLaunchKernelGGL(k_phase_2bit<8>, dim3(grid), dim3(block), (size_t)block * 8u, s, a, R);
+    else
+        hipLaunchKernelGGL(k_phase_2bit<1>, dim3(grid), dim3(block), (size_t)block * 8u, s, a, R);
     return hipGetLastError();
 }
 
@@ -461,6 +716,35 @@ hipError_t launch_observables(const void *state, int L, int encoding, unsigned l
         hipLaunchKernelGGL(k_obs_int8, dim3((unsigned)grid), dim3(256), 0, s, (const int8_t *)state, L, obs);
     else
         hipLaunchKernelGGL(k_obs_2bit, dim3((unsigned)grid), dim3(256), 0, s, (const uint32_t *)state, L, obs);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_lds(const BatchArgs &a, int max_L, hipStream_t s)
+{
+    const uint32_t calls = (uint32_t)max_L * (uint32_t)max_L / 16u;
+    uint32_t block = calls < 1024u ? ((calls + 63u) / 64u) * 64u : 1024u;
+    if (block < 64u) block = 64u;
+    const size_t lds = lds_state_words(max_L) * 4u;
+    static bool attr_set = false;
+    if (!attr_set) {
+        // allow more than the default 64 KiB of dynamic LDS (L = 512 needs 64 KiB + tables)
+        (void)hipFuncSetAttribute((const void *)k_sweep_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(lds_state_words(kLdsMaxL) * 4u));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_sweep_lds, dim3((unsigned)a.count), dim3(block), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(LatDesc *desc, uint32_t sweeps, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, desc, sweeps);
+    return hipGetLastError();
+}
+
+hipError_t launch_observables_batch(const BatchArgs &a, unsigned long long *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_obs_batch, dim3((unsigned)a.count), dim3(256), 0, s, a, out);
     return hipGetLastError();
 }
 

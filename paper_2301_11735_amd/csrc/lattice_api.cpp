@@ -30,7 +30,8 @@ struct lattice {
     void *d_state = nullptr;
     uint8_t *d_scratch = nullptr;
     hipStream_t stream = nullptr;
-    lat::Tuning2Bit tuning{0, 0};
+    lat::Tuning2Bit tuning{0, 0, 0};
+    bool phase_kernels = false;  // big lattice, or forced: one launch per phase
     uint32_t magic = 0;
 };
 
@@ -142,20 +143,33 @@ void build_threshold_table(double Delta, double V, double J, double T, std::vect
             }
 }
 
-// Device threshold table: the reachable slices nD in {-2, 0, 2}, each entry
-// paired with the packed triple an accepted move adds to the tracker.
+// Packed triple an accepted move adds to the per-thread tracker.
+uint32_t packed_triple(int nD, int nV, int nJ)
+{
+    return (1u << 27) | ((uint32_t)(nD + 2) << 20) | ((uint32_t)(nV + 16) << 10) | (uint32_t)(nJ + 16);
+}
+
+uint32_t threshold_of(const std::vector<uint32_t> &tab, int nD, int nV, int nJ)
+{
+    return tab[(size_t)(nD + 2) * (kTabV * kTabJ) + (size_t)(nV + 16) * kTabJ + (size_t)(nJ + 16)];
+}
+
+// Device threshold table: the reachable triples only (regions in kernels.h),
+// each entry paired with its packed tracker triple.
 void build_device_table(const std::vector<uint32_t> &tab, std::vector<uint32_t> &dev)
 {
     dev.assign(2 * (size_t)kDevTabEntries, 0u);
-    for (int s = 0; s < 3; ++s) {
-        const int nD = 2 * s - 2;
-        for (int nV = -16; nV <= 16; ++nV)
-            for (int nJ = -16; nJ <= 16; ++nJ) {
-                const size_t i = (size_t)s * (kTabV * kTabJ) + (size_t)(nV + 16) * kTabJ + (size_t)(nJ + 16);
-                dev[2 * i] = tab[(size_t)(nD + 2) * (kTabV * kTabJ) + (size_t)(nV + 16) * kTabJ + (size_t)(nJ + 16)];
-                dev[2 * i + 1] = (1u << 27) | ((uint32_t)(nD + 2) << 20) | ((uint32_t)(nV + 16) << 10) |
-                                 (uint32_t)(nJ + 16);
-            }
+    auto put = [&](size_t i, int nD, int nV, int nJ) {
+        dev[2 * i] = threshold_of(tab, nD, nV, nJ);
+        dev[2 * i + 1] = packed_triple(nD, nV, nJ);
+    };
+    for (int s = 0; s < 3; ++s)
+        for (int nV = -8; nV <= 8; ++nV)
+            for (int nJ = -8; nJ <= 8; ++nJ)
+                put((size_t)s * kDevSlice + (size_t)(nV + 8) * 17 + (size_t)(nJ + 8), 2 * s - 2, nV, nJ);
+    for (int v = -16; v <= 16; ++v) {
+        put((size_t)kDevVLine + (size_t)(v + 16), 0, v, 0);
+        put((size_t)kDevJLine + (size_t)(v + 16), 0, 0, v);
     }
 }
 
@@ -165,8 +179,11 @@ void build_device_table(const std::vector<uint32_t> &tab, std::vector<uint32_t> 
 //   q=+1: (2,0) (2,1) (0,2) (1,2)
 //   q= 0: (2,3) (3,2) (0,0) (1,1) (0,1) (1,0)
 //   q=-1: (3,0) (3,1) (0,3) (1,3),
-// and the coefficients that turn the neighbour sums into the table index.
-// The frozen states (|q| = 2) get one null move with index of (0, 0, 0).
+// and the coefficients that turn the neighbour sums (each offset by +4) into
+// the device-table index of the move's (nD, nV, nJ).  Since the pair keeps its
+// charge, dS_a + dS_b = 0 and the +4 offsets of the charge sums cancel; the
+// spin offsets 4*(dsig_a + dsig_b) are folded into C.  The frozen states
+// (|q| = 2) get one null move.
 void build_transition_table(std::vector<uint32_t> &trans)
 {
     static const int kS[4] = {0, 0, 1, -1}, kG[4] = {1, -1, 0, 0};
@@ -174,7 +191,7 @@ void build_transition_table(std::vector<uint32_t> &trans)
     static const int kZero[6][2] = {{2, 3}, {3, 2}, {0, 0}, {1, 1}, {0, 1}, {1, 0}};
     static const int kMinus1[4][2] = {{3, 0}, {3, 1}, {0, 3}, {1, 3}};
     trans.assign(2 * (size_t)kTransEntries, 0u);
-    const int center = 1 * (kTabV * kTabJ) + 16 * kTabJ + 16;
+    auto i8 = [](int v) { return (uint32_t)(uint8_t)(int8_t)v; };
     for (int st = 0; st < 16; ++st) {
         const int ca = st & 3, cb = st >> 2, q = kS[ca] + kS[cb];
         const int (*set)[2] = q == 1 ? kPlus1 : (q == 0 ? kZero : (q == -1 ? kMinus1 : nullptr));
@@ -184,24 +201,30 @@ void build_transition_table(std::vector<uint32_t> &trans)
             const int dSa = kS[a1] - kS[ca], dSb = kS[b1] - kS[cb];
             const int dGa = kG[a1] - kG[ca], dGb = kG[b1] - kG[cb];
             const int nD = kS[a1] * kS[a1] + kS[b1] * kS[b1] - kS[ca] * kS[ca] - kS[cb] * kS[cb];
-            // idx = (nD/2+1)*1089 + (nV+16)*33 + (nJ+16); with the +4 offsets of the
-            // packed sums, 33*(dSa*4 + dSb*4) vanishes (dSa + dSb = 0) and
-            // dGa*4 + dGb*4 is subtracted here.
-            const int C = center + (nD / 2) * (kTabV * kTabJ) - 4 * (dGa + dGb);
-            const uint32_t coef = (uint32_t)(uint8_t)(int8_t)(33 * dSa) | ((uint32_t)(uint8_t)(int8_t)(33 * dSb) << 8) |
-                                  ((uint32_t)(uint8_t)(int8_t)dGa << 16) | ((uint32_t)(uint8_t)(int8_t)dGb << 24);
-            const uint32_t meta = (uint32_t)C | ((uint32_t)(a1 | (b1 << 2)) << 16);
+            uint32_t coef;
+            int C;
+            if (dSa == 2 || dSa == -2) {  // charge swap: V line, nJ = 0
+                coef = i8(dSa) | (i8(dSb) << 8);
+                C = kDevVLine + 16;
+            } else if (dGa == 2 || dGa == -2 || dGb == 2 || dGb == -2) {  // spin change: J line, nV = 0
+                coef = (i8(dGa) << 16) | (i8(dGb) << 24);
+                C = kDevJLine + 16 - 4 * (dGa + dGb);
+            } else {  // |dS|, |dsig| <= 1: slice nD/2 + 1
+                coef = i8(17 * dSa) | (i8(17 * dSb) << 8) | (i8(dGa) << 16) | (i8(dGb) << 24);
+                C = (nD / 2 + 1) * kDevSlice + 8 * 17 + 8 - 4 * (dGa + dGb);
+            }
             trans[2 * (size_t)(st * 6 + j)] = coef;
-            trans[2 * (size_t)(st * 6 + j) + 1] = meta;
+            trans[2 * (size_t)(st * 6 + j) + 1] = (uint32_t)C | ((uint32_t)(a1 | (b1 << 2)) << 16);
         }
     }
 }
 
 Tuning2Bit tuning_from_env()
 {
-    Tuning2Bit t{0, 0};
+    Tuning2Bit t{0, 0, 0};
     if (const char *v = std::getenv("LATTICE_2BIT_ROWS")) t.rows_per_block = std::atoi(v);
     if (const char *v = std::getenv("LATTICE_2BIT_BLOCKS_PER_CU")) t.blocks_per_cu = std::atoi(v);
+    if (const char *v = std::getenv("LATTICE_2BIT_WAVES")) t.waves_hint = std::atoi(v);
     return t;
 }
 
@@ -268,7 +291,9 @@ Schedule sweep_schedule(int32_t L, uint64_t seed, uint64_t s)
 
 bool live(const lattice *h) { return h != nullptr && h->magic == kMagic; }
 
-int enqueue_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
+// Host-scheduled path: four phase launches per sweep, then the device-side
+// sweep counter is advanced to match.
+int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
 {
     PhaseArgs a{};
     a.state = h->d_state;
@@ -293,8 +318,56 @@ int enqueue_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
             if (e != hipSuccess) return hip_fail(e, "phase kernel launch");
         }
     }
+    if (sweeps > 0) {
+        const hipError_t e = launch_advance((LatDesc *)(h->d_scratch + kScrDesc), sweeps, stream);
+        if (e != hipSuccess) return hip_fail(e, "advance kernel launch");
+    }
     h->done += sweeps;
     return LAT_OK;
+}
+
+// Batched path: lattices resident in LDS, up to kMaxBatch per launch.
+int enqueue_lds_sweeps(lattice *const *hs, int32_t count, uint32_t sweeps, hipStream_t stream)
+{
+    for (int32_t b = 0; b < count; b += kMaxBatch) {
+        BatchArgs a{};
+        a.count = std::min<int32_t>(kMaxBatch, count - b);
+        a.sweeps = sweeps;
+        int max_L = 0;
+        for (int i = 0; i < a.count; ++i) {
+            a.scratch[i] = hs[b + i]->d_scratch;
+            max_L = std::max(max_L, hs[b + i]->L);
+        }
+        const hipError_t e = launch_sweep_lds(a, max_L, stream);
+        if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
+        for (int i = 0; i < a.count; ++i) hs[b + i]->done += sweeps;
+    }
+    return LAT_OK;
+}
+
+int enqueue_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
+{
+    if (sweeps == 0) return LAT_OK;
+    if (h->phase_kernels) return enqueue_phase_sweeps(h, sweeps, stream);
+    lattice *one[1] = {h};
+    return enqueue_lds_sweeps(one, 1, sweeps, stream);
+}
+
+// v = (tracker nD, nV, nJ, sum S, sum S^2, bonds SS, bonds ss, M, M_st, C_st).
+void fill_obs(const lattice *h, const int64_t *v, lat_obs *out)
+{
+    out->sweep = h->done;
+    out->track_nD = v[0];
+    out->track_nV = v[1];
+    out->track_nJ = v[2];
+    out->sum_S = v[3];
+    out->n_charged = v[4];
+    out->bond_SS = v[5];
+    out->bond_ss = v[6];
+    out->M = v[7];
+    out->M_stag = v[8];
+    out->C_stag = v[9];
+    out->E = h->Delta * (double)out->n_charged + h->V * (double)out->bond_SS + 0.25 * h->J * (double)out->bond_ss;
 }
 
 }  // namespace
@@ -378,7 +451,18 @@ int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void 
     h->d_scratch = (uint8_t *)d_scratch;
     h->stream = (hipStream_t)hip_stream;
     h->tuning = tuning_from_env();
+    {
+        const char *force = std::getenv("LATTICE_FORCE_PHASE_KERNELS");
+        h->phase_kernels = p->L > kLdsMaxL || (force && std::atoi(force) != 0);
+    }
     h->magic = kMagic;
+    LatDesc desc{};
+    desc.state = d_state;
+    desc.L = p->L;
+    desc.enc = p->encoding;
+    desc.key0 = (uint32_t)p->seed;
+    desc.key1 = (uint32_t)(p->seed >> 32);
+    desc.next_sweep = p->start_sweep;
 
     hipError_t e = hipMemcpyAsync(d_state, dev.data(), dev.size(), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
@@ -386,6 +470,8 @@ int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void 
                            h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->d_scratch + kScrTrans, trans.data(), trans.size() * 4, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->d_scratch + kScrDesc, &desc, sizeof(desc), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = launch_zero_i64((unsigned long long *)(h->d_scratch + kScrTrack), 10, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // host staging buffers die with this frame
     if (e != hipSuccess) {
@@ -408,10 +494,47 @@ int lattice_sweep_batch(lattice *const *hs, int32_t count, uint32_t sweeps, void
     if (count < 0 || (count > 0 && !hs)) return fail(LAT_EINVAL, "bad batch");
     for (int32_t i = 0; i < count; ++i)
         if (!live(hs[i])) return fail(LAT_ESTATE, "null or destroyed handle in batch");
-    for (int32_t i = 0; i < count; ++i) {
-        const int rc = enqueue_sweeps(hs[i], sweeps, (hipStream_t)hip_stream);
-        if (rc) return rc;
+    {
+        std::vector<const lattice *> seen(hs, hs + count);
+        std::sort(seen.begin(), seen.end());
+        if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+            return fail(LAT_EINVAL, "a lattice appears twice in the batch");
     }
+    if (sweeps == 0) return LAT_OK;
+    std::vector<lattice *> small;
+    for (int32_t i = 0; i < count; ++i) {
+        if (hs[i]->phase_kernels) {
+            const int rc = enqueue_phase_sweeps(hs[i], sweeps, (hipStream_t)hip_stream);
+            if (rc) return rc;
+        } else {
+            small.push_back(hs[i]);
+        }
+    }
+    return enqueue_lds_sweeps(small.data(), (int32_t)small.size(), sweeps, (hipStream_t)hip_stream);
+}
+
+int lattice_observables_batch(lattice *const *hs, int32_t count, void *d_out, size_t out_bytes, lat_obs *out,
+                              void *hip_stream)
+{
+    if (count < 0 || (count > 0 && (!hs || !out || !d_out))) return fail(LAT_EINVAL, "bad batch");
+    if (out_bytes < (size_t)count * 80u) return fail(LAT_ENOMEM, "output buffer smaller than 80 bytes per lattice");
+    for (int32_t i = 0; i < count; ++i)
+        if (!live(hs[i])) return fail(LAT_ESTATE, "null or destroyed handle in batch");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    unsigned long long *dev = (unsigned long long *)d_out;
+    for (int32_t b = 0; b < count; b += kMaxBatch) {
+        BatchArgs a{};
+        a.count = std::min<int32_t>(kMaxBatch, count - b);
+        for (int i = 0; i < a.count; ++i) a.scratch[i] = hs[b + i]->d_scratch;
+        const hipError_t e = launch_observables_batch(a, dev + 10 * (size_t)b, stream);
+        if (e != hipSuccess) return hip_fail(e, "batched observables launch");
+    }
+    std::vector<int64_t> v((size_t)count * 10);
+    hipError_t e = hipSuccess;
+    if (count > 0) e = hipMemcpyAsync(v.data(), d_out, v.size() * 8, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "lattice_observables_batch");
+    for (int32_t i = 0; i < count; ++i) fill_obs(hs[i], &v[10 * (size_t)i], &out[i]);
     return LAT_OK;
 }
 
@@ -426,18 +549,7 @@ int lattice_observables(lattice *h, lat_obs *out)
     if (e == hipSuccess) e = hipMemcpyAsync(v, track, sizeof(v), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "lattice_observables");
-    out->sweep = h->done;
-    out->track_nD = v[0];
-    out->track_nV = v[1];
-    out->track_nJ = v[2];
-    out->sum_S = v[3];
-    out->n_charged = v[4];
-    out->bond_SS = v[5];
-    out->bond_ss = v[6];
-    out->M = v[7];
-    out->M_stag = v[8];
-    out->C_stag = v[9];
-    out->E = h->Delta * (double)out->n_charged + h->V * (double)out->bond_SS + 0.25 * h->J * (double)out->bond_ss;
+    fill_obs(h, v, out);
     return LAT_OK;
 }
 

@@ -172,3 +172,86 @@ def test_large_config_invariants():
         assert o.track_nD == o.n_charged - o0.n_charged
         assert o.track_nV == o.bond_SS - o0.bond_SS
         assert o.track_nJ == o.bond_ss - o0.bond_ss
+
+
+# ---------------------------------------------------------------- both kernel paths, batches
+@pytest.mark.parametrize("spec", [
+    SMALL.with_(L=12, n=0.2, seed=61),
+    SMALL.with_(L=32, seed=62),
+    SMALL.with_(L=100, Delta=-0.7, V=-0.3, T=1.7, seed=63),
+    SMALL.with_(L=64, encoding=1, seed=64),
+    SMALL.with_(L=192, encoding=1, T=0.5, seed=65),
+], ids=lambda s: f"enc{s.encoding}-L{s.L}")
+def test_phase_kernel_path_matches_oracle(spec, monkeypatch):
+    """Lattices with L <= 512 normally run resident in LDS; force the
+    one-launch-per-phase kernels so both paths stay checked at small sizes."""
+    monkeypatch.setenv("LATTICE_FORCE_PHASE_KERNELS", "1")
+    _run_parity(spec, [1, 3, 10])
+
+
+def _make(spec):
+    return lat.Lattice(spec.L, spec.n, spec.Delta, spec.V, spec.J, spec.T, spec.seed, encoding=spec.encoding,
+                       n_charged=spec.n_charged)
+
+
+def _oracle(spec):
+    return oracle.OracleLattice(spec.L, spec.n, spec.Delta, spec.V, spec.J, spec.T, spec.seed,
+                                n_charged=spec.n_charged)
+
+
+def test_mixed_batch_matches_oracle():
+    """One batched launch over lattices of different L, encodings and
+    parameters: every lattice bit-exact against its own oracle run."""
+    _say("case mixed batch")
+    rng = np.random.default_rng(5)
+    specs = []
+    for i, (L, enc) in enumerate([(4, 0), (8, 0), (12, 0), (32, 0), (64, 1), (100, 0), (128, 1), (192, 1),
+                                  (256, 0), (256, 1), (512, 1), (64, 0)]):
+        specs.append(SMALL.with_(L=L, encoding=enc, seed=700 + i, n=float(rng.uniform(-0.3, 0.3)),
+                                 Delta=float(rng.uniform(-1, 1)), V=float(rng.uniform(-1, 1)),
+                                 T=float(rng.uniform(0.2, 2.5))))
+    gs = [_make(s) for s in specs]
+    os_ = [_oracle(s) for s in specs]
+    obs = lat.BatchObservables(len(gs))
+    for k in (7, 4):
+        lat.sweep_batch(gs, k)
+        for o in os_:
+            o.sweeps(k)
+        got = obs(gs)
+        for s, g, o, go in zip(specs, gs, os_, got):
+            assert np.array_equal(g.read_state(), o.codes), f"L={s.L} enc={s.encoding}"
+            assert go.ints() == o.observables().tolist()
+            assert [go.track_nD, go.track_nV, go.track_nJ] == o.track.tolist()
+            assert go.E == o.energy()
+
+
+def test_batched_config_subset_matches_oracle():
+    """The batched workload (L=128, 2-bit, 32 temperatures x 8 densities):
+    every 16th lattice, bit-exact after 60 sweeps done in one batched launch."""
+    _say("case batched subset")
+    specs = workloads.batched_specs()[::16]
+    gs = [_make(s) for s in specs]
+    lat.sweep_batch(gs, 60)
+    for s, g in zip(specs, gs):
+        o = _oracle(s)
+        o.sweeps(60)
+        assert np.array_equal(g.read_state(), o.codes), f"seed {s.seed}"
+
+
+def test_batched_config_invariants():
+    """All 256 lattices of the batched workload: charge exact and tracker equal
+    to the recomputed energy after 200 sweeps."""
+    _say("case batched invariants")
+    specs = workloads.batched_specs()
+    gs = [_make(s) for s in specs]
+    obs = lat.BatchObservables(len(gs))
+    first = obs(gs)
+    for _ in range(2):
+        lat.sweep_batch(gs, 100)
+        now = obs(gs)
+        for s, a, b in zip(specs, first, now):
+            Q, Nc = lat.charge_target(s.L, s.n)
+            assert b.sum_S == Q
+            assert b.track_nD == b.n_charged - a.n_charged
+            assert b.track_nV == b.bond_SS - a.bond_SS
+            assert b.track_nJ == b.bond_ss - a.bond_ss
