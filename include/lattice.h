@@ -142,6 +142,63 @@ int lattice_sweep_batch(lattice *const *hs, int32_t count, uint32_t sweeps, void
 int lattice_observables_batch(lattice *const *hs, int32_t count, void *d_out, size_t out_bytes, lat_obs *out,
                               void *hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Serving: simulation requests that arrive while others run.  The server
+ * admits queued requests, in arrival order, into the caller's device pool when
+ * a slot and pool memory are free; every call of lat_server_step advances all
+ * resident requests together in one batched launch (section 3.2: lattice
+ * copies processed together), each by about `quantum_updates` site updates
+ * (max(1, quantum_updates / N) sweeps, capped by what the request still
+ * needs), then harvests the finished ones and frees their memory, so new
+ * requests join between steps.  A request's result is bit-identical to
+ * running it alone with lattice_create/lattice_sweep.  Served lattices need
+ * L <= 512.  Timestamps are seconds of the monotonic clock (CLOCK_MONOTONIC).
+ */
+typedef struct lat_server lat_server;
+
+#define LAT_REQ_QUEUED 0
+#define LAT_REQ_RESIDENT 1
+#define LAT_REQ_FINISHED 2
+
+typedef struct {
+    uint64_t id;
+    int32_t status;          /* LAT_REQ_* */
+    uint32_t sweeps_total;
+    uint32_t sweeps_done;
+    double t_submit, t_admit, t_finish;
+    lat_obs obs;             /* valid once finished */
+} lat_request_info;
+
+typedef struct {
+    int32_t queued, resident;
+    uint64_t pool_used;      /* bytes of the pool held by resident lattices and the reserved slot */
+    uint64_t steps;          /* lat_server_step calls that launched work */
+    uint64_t site_updates;   /* site updates launched so far */
+} lat_server_counters;
+
+/* d_pool: caller-owned device memory the server carves lattices from (each
+ * takes lattice_state_bytes + lattice_scratch_bytes, 256-byte aligned; the
+ * first 80*max_slots bytes, rounded up, are reserved for observables).
+ * Errors: LAT_EINVAL, LAT_ENOMEM. */
+int lat_server_create(void *d_pool, size_t pool_bytes, int32_t max_slots, uint64_t quantum_updates,
+                      void *hip_stream, lat_server **out);
+/* Queue a request to run `sweeps` sweeps of the lattice p describes (p is
+ * copied).  keep_state != 0 keeps the final codes for lat_server_poll.
+ * Errors: LAT_ESTATE, LAT_EINVAL. */
+int lat_server_submit(lat_server *s, const lat_params *p, uint32_t sweeps, int32_t keep_state, uint64_t *id);
+/* Admit, advance every resident request once, harvest finished ones.
+ * Synchronises the server's stream when requests are admitted or finish.
+ * Errors: LAT_ESTATE, LAT_EHIP, and lattice_create's errors for a request. */
+int lat_server_step(lat_server *s, int32_t *n_finished);
+/* State of a request; final_codes (N host codes, may be NULL) is filled for a
+ * finished request submitted with keep_state.  Errors: LAT_ESTATE, LAT_EINVAL. */
+int lat_server_poll(lat_server *s, uint64_t id, lat_request_info *out, int8_t *final_codes);
+/* Forget a finished request.  Errors: LAT_ESTATE, LAT_EINVAL. */
+int lat_server_release(lat_server *s, uint64_t id);
+int lat_server_stats(lat_server *s, lat_server_counters *out);
+/* Destroy the server and any resident lattices (caller memory untouched). */
+int lat_server_destroy(lat_server *s);
+
 /* Release the handle (host memory only; caller buffers are untouched). */
 int lattice_destroy(lattice *h);
 

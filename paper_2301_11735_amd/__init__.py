@@ -30,7 +30,15 @@ EXPORTS = (
     "lattice_observables_batch",
     "lattice_destroy",
     "lattice_last_error",
+    "lat_server_create",
+    "lat_server_submit",
+    "lat_server_step",
+    "lat_server_poll",
+    "lat_server_release",
+    "lat_server_stats",
+    "lat_server_destroy",
 )
+REQ_QUEUED, REQ_RESIDENT, REQ_FINISHED = 0, 1, 2
 
 
 class LatParams(ctypes.Structure):
@@ -73,6 +81,29 @@ class LatObs(ctypes.Structure):
         return [self.sum_S, self.n_charged, self.bond_SS, self.bond_ss, self.M, self.M_stag, self.C_stag]
 
 
+class LatRequestInfo(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_uint64),
+        ("status", ctypes.c_int32),
+        ("sweeps_total", ctypes.c_uint32),
+        ("sweeps_done", ctypes.c_uint32),
+        ("t_submit", ctypes.c_double),
+        ("t_admit", ctypes.c_double),
+        ("t_finish", ctypes.c_double),
+        ("obs", LatObs),
+    ]
+
+
+class LatServerStats(ctypes.Structure):
+    _fields_ = [
+        ("queued", ctypes.c_int32),
+        ("resident", ctypes.c_int32),
+        ("pool_used", ctypes.c_uint64),
+        ("steps", ctypes.c_uint64),
+        ("site_updates", ctypes.c_uint64),
+    ]
+
+
 class LatticeError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"liblattice error {code}: {msg}")
@@ -111,6 +142,21 @@ def lib() -> ctypes.CDLL:
         L.lattice_observables_batch.restype = ctypes.c_int
         L.lattice_destroy.argtypes = [vp]
         L.lattice_destroy.restype = ctypes.c_int
+        L.lat_server_create.argtypes = [vp, sz, ctypes.c_int32, ctypes.c_uint64, vp, ctypes.POINTER(vp)]
+        L.lat_server_create.restype = ctypes.c_int
+        L.lat_server_submit.argtypes = [vp, ctypes.POINTER(LatParams), ctypes.c_uint32, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_uint64)]
+        L.lat_server_submit.restype = ctypes.c_int
+        L.lat_server_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+        L.lat_server_step.restype = ctypes.c_int
+        L.lat_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(LatRequestInfo), ctypes.POINTER(ctypes.c_int8)]
+        L.lat_server_poll.restype = ctypes.c_int
+        L.lat_server_release.argtypes = [vp, ctypes.c_uint64]
+        L.lat_server_release.restype = ctypes.c_int
+        L.lat_server_stats.argtypes = [vp, ctypes.POINTER(LatServerStats)]
+        L.lat_server_stats.restype = ctypes.c_int
+        L.lat_server_destroy.argtypes = [vp]
+        L.lat_server_destroy.restype = ctypes.c_int
         L.lattice_last_error.argtypes = []
         L.lattice_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -235,3 +281,63 @@ class BatchObservables:
         _check(lib().lattice_observables_batch(_handles(lattices), n, self.buf.data_ptr(), self.buf.numel(), out,
                                                _stream_handle(stream)))
         return list(out)[:n]
+
+
+class Server:
+    """Continuous-batching request server (lat_server_*) over a torch-owned
+    device pool of `pool_bytes`."""
+
+    def __init__(self, pool_bytes: int, max_slots: int = 256, quantum_updates: int = 1 << 22, device: str = "cuda",
+                 stream=None):
+        import torch
+
+        self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device=device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(lib().lat_server_create(self.pool.data_ptr(), pool_bytes, max_slots, quantum_updates,
+                                       _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self._sizes = {}
+
+    def submit(self, L, n, Delta, V, J, T, seed, sweeps, encoding=ENC_2BIT, n_charged=-1, keep_state=False) -> int:
+        p = LatParams(L=L, encoding=encoding, n=n, Delta=Delta, V=V, J=J, T=T, seed=seed, n_charged=n_charged,
+                      start_sweep=0, init_codes=None)
+        rid = ctypes.c_uint64()
+        _check(lib().lat_server_submit(self._h, ctypes.byref(p), sweeps, int(keep_state), ctypes.byref(rid)))
+        self._sizes[rid.value] = L * L
+        return rid.value
+
+    def step(self) -> int:
+        n = ctypes.c_int32()
+        _check(lib().lat_server_step(self._h, ctypes.byref(n)))
+        return n.value
+
+    def poll(self, rid: int, with_state: bool = False):
+        info = LatRequestInfo()
+        codes = None
+        ptr = None
+        if with_state:
+            codes = np.empty(self._sizes[rid], dtype=np.int8)
+            ptr = codes.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+        _check(lib().lat_server_poll(self._h, rid, ctypes.byref(info), ptr))
+        return (info, codes) if with_state else info
+
+    def release(self, rid: int):
+        _check(lib().lat_server_release(self._h, rid))
+        self._sizes.pop(rid, None)
+
+    def stats(self) -> LatServerStats:
+        st = LatServerStats()
+        _check(lib().lat_server_stats(self._h, ctypes.byref(st)))
+        return st
+
+    def destroy(self):
+        if self._h is not None:
+            _check(lib().lat_server_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

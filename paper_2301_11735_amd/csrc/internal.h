@@ -1,0 +1,40 @@
+// Library-internal declarations shared by the host sources (lattice_api.cpp,
+// server.cpp).  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/lattice.h"
+#include "kernels.h"
+
+struct lattice {
+    int L = 0, enc = 0;
+    int64_t N = 0, Q = 0, Nc = 0;
+    double n = 0, Delta = 0, V = 0, J = 0, T = 1;
+    uint64_t seed = 0, start_sweep = 0, done = 0;
+    void *d_state = nullptr;
+    uint8_t *d_scratch = nullptr;
+    hipStream_t stream = nullptr;
+    lat::Tuning2Bit tuning{0, 0, 0};
+    bool phase_kernels = false;  // big lattice, or forced: one launch per phase
+    uint32_t magic = 0;
+};
+
+namespace lat {
+namespace detail {
+
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+bool live(const lattice *h);
+// Advance lattices resident in LDS; lattice i by sweeps[i] (null: `uniform`).
+int enqueue_lds_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps, uint32_t uniform,
+                       hipStream_t stream);
+int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream);
+// v = (tracker nD, nV, nJ, sum S, sum S^2, bonds SS, bonds ss, M, M_st, C_st).
+void fill_obs(const lattice *h, const int64_t *v, lat_obs *out);
+
+}  // namespace detail
+}  // namespace lat

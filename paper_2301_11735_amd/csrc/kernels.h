@@ -55,12 +55,12 @@ struct LatDesc {
 constexpr int kLdsMaxL = 512;
 inline size_t lds_state_words(int L) { return (size_t)8 * (L / 2) * ((L / 4 + 15) / 16); }
 
-// One launch of the batched kernel: block b advances lattice b by `sweeps`.
+// One launch of the batched kernel: block b advances lattice b by sweeps[b].
 constexpr int kMaxBatch = 256;
 struct BatchArgs {
     int count;
-    uint32_t sweeps;
     uint8_t *scratch[kMaxBatch];
+    uint32_t sweeps[kMaxBatch];
 };
 
 // One phase of one sweep: phase p, displacement D = (r + 4m, 1 + 2k).

@@ -516,7 +516,8 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(BatchArgs args)
 
     const uint32_t n_calls = (uint32_t)L * (uint32_t)L / 16u;
     int tr[3] = {0, 0, 0};
-    for (uint64_t s = d.next_sweep; s < d.next_sweep + args.sweeps; ++s) {
+    const uint32_t my_sweeps = args.sweeps[blockIdx.x];
+    for (uint64_t s = d.next_sweep; s < d.next_sweep + my_sweeps; ++s) {
         int r, mm[4], kk[4];
         device_schedule(L, d.key0, d.key1, s, r, mm, kk);
         for (int p = 0; p < 4; ++p) {
@@ -572,7 +573,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(BatchArgs args)
             dst[i] = (int8_t)lds_code(lat, g, 4 * (y & 1) + (x & 3), y >> 1, x >> 2);
         }
     }
-    if (threadIdx.x == 0) ((LatDesc *)(scr + kScrDesc))->next_sweep = d.next_sweep + args.sweeps;
+    if (threadIdx.x == 0) ((LatDesc *)(scr + kScrDesc))->next_sweep = d.next_sweep + my_sweeps;
     block_reduce_add<3>(tr, (unsigned long long *)(scr + kScrTrack));
 }
 

@@ -17,23 +17,12 @@
 #include <vector>
 
 #include "../../include/lattice.h"
+#include "internal.h"
 #include "kernels.h"
 #include "philox.h"
 
 using namespace lat;
-
-struct lattice {
-    int L = 0, enc = 0;
-    int64_t N = 0, Q = 0, Nc = 0;
-    double n = 0, Delta = 0, V = 0, J = 0, T = 1;
-    uint64_t seed = 0, start_sweep = 0, done = 0;
-    void *d_state = nullptr;
-    uint8_t *d_scratch = nullptr;
-    hipStream_t stream = nullptr;
-    lat::Tuning2Bit tuning{0, 0, 0};
-    bool phase_kernels = false;  // big lattice, or forced: one launch per phase
-    uint32_t magic = 0;
-};
+using namespace lat::detail;
 
 namespace {
 
@@ -41,6 +30,11 @@ constexpr uint32_t kMagic = 0x1A771CEu;
 constexpr int kMaxL = 32768;
 
 thread_local std::string g_err;
+
+}  // namespace
+
+namespace lat {
+namespace detail {
 
 int fail(int code, const std::string &msg)
 {
@@ -52,6 +46,13 @@ int hip_fail(hipError_t e, const char *what)
 {
     return fail(LAT_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
+
+bool live(const lattice *h) { return h != nullptr && h->magic == kMagic; }
+
+}  // namespace detail
+}  // namespace lat
+
+namespace {
 
 bool valid_geometry(int32_t L, int32_t enc)
 {
@@ -289,7 +290,10 @@ Schedule sweep_schedule(int32_t L, uint64_t seed, uint64_t s)
     return sc;
 }
 
-bool live(const lattice *h) { return h != nullptr && h->magic == kMagic; }
+}  // namespace
+
+namespace lat {
+namespace detail {
 
 // Host-scheduled path: four phase launches per sweep, then the device-side
 // sweep counter is advanced to match.
@@ -327,30 +331,23 @@ int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
 }
 
 // Batched path: lattices resident in LDS, up to kMaxBatch per launch.
-int enqueue_lds_sweeps(lattice *const *hs, int32_t count, uint32_t sweeps, hipStream_t stream)
+int enqueue_lds_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps, uint32_t uniform,
+                       hipStream_t stream)
 {
     for (int32_t b = 0; b < count; b += kMaxBatch) {
         BatchArgs a{};
         a.count = std::min<int32_t>(kMaxBatch, count - b);
-        a.sweeps = sweeps;
         int max_L = 0;
         for (int i = 0; i < a.count; ++i) {
             a.scratch[i] = hs[b + i]->d_scratch;
+            a.sweeps[i] = sweeps ? sweeps[b + i] : uniform;
             max_L = std::max(max_L, hs[b + i]->L);
         }
         const hipError_t e = launch_sweep_lds(a, max_L, stream);
         if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
-        for (int i = 0; i < a.count; ++i) hs[b + i]->done += sweeps;
+        for (int i = 0; i < a.count; ++i) hs[b + i]->done += a.sweeps[i];
     }
     return LAT_OK;
-}
-
-int enqueue_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
-{
-    if (sweeps == 0) return LAT_OK;
-    if (h->phase_kernels) return enqueue_phase_sweeps(h, sweeps, stream);
-    lattice *one[1] = {h};
-    return enqueue_lds_sweeps(one, 1, sweeps, stream);
 }
 
 // v = (tracker nD, nV, nJ, sum S, sum S^2, bonds SS, bonds ss, M, M_st, C_st).
@@ -368,6 +365,19 @@ void fill_obs(const lattice *h, const int64_t *v, lat_obs *out)
     out->M_stag = v[8];
     out->C_stag = v[9];
     out->E = h->Delta * (double)out->n_charged + h->V * (double)out->bond_SS + 0.25 * h->J * (double)out->bond_ss;
+}
+
+}  // namespace detail
+}  // namespace lat
+
+namespace {
+
+int enqueue_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
+{
+    if (sweeps == 0) return LAT_OK;
+    if (h->phase_kernels) return enqueue_phase_sweeps(h, sweeps, stream);
+    lattice *one[1] = {h};
+    return enqueue_lds_sweeps(one, 1, nullptr, sweeps, stream);
 }
 
 }  // namespace
@@ -510,7 +520,7 @@ int lattice_sweep_batch(lattice *const *hs, int32_t count, uint32_t sweeps, void
             small.push_back(hs[i]);
         }
     }
-    return enqueue_lds_sweeps(small.data(), (int32_t)small.size(), sweeps, (hipStream_t)hip_stream);
+    return enqueue_lds_sweeps(small.data(), (int32_t)small.size(), nullptr, sweeps, (hipStream_t)hip_stream);
 }
 
 int lattice_observables_batch(lattice *const *hs, int32_t count, void *d_out, size_t out_bytes, lat_obs *out,

@@ -19,7 +19,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(lat.LIB_PATH), reason="liblat
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lattice_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b((?:lattice|lat_server)_[a-z_]+)\s*\(", text)))
 
 
 def test_header_declares_the_binding_exports():

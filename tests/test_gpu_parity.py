@@ -255,3 +255,37 @@ def test_batched_config_invariants():
             assert b.track_nD == b.n_charged - a.n_charged
             assert b.track_nV == b.bond_SS - a.bond_SS
             assert b.track_nJ == b.bond_ss - a.bond_ss
+
+
+# ---------------------------------------------------------------- serving
+def test_served_results_equal_alone_and_oracle():
+    """Requests served in a mix (continuous batching, small pool so requests
+    queue) give the same final state and observables as each run alone, and
+    as the oracle."""
+    _say("case serving")
+    from paper_2301_11735_amd import serve as serve_mod
+
+    reqs = workloads.request_stream(rate_per_s=60.0, duration_s=1.5, seed=11, sizes=(64, 128),
+                                    sweep_range=(20, 120))
+    assert len(reqs) > 40
+    pool = 1 << 20   # about 12 resident L=128 lattices: admission has to queue
+    done, wall, st = serve_mod.serve(reqs, pool, slots=16, quantum=1 << 16, keep_state=True, progress=False)
+    assert len(done) == len(reqs)
+    rng = np.random.default_rng(3)
+    for k in rng.choice(len(reqs), size=8, replace=False):
+        r = reqs[int(k)]
+        s = r.spec
+        g = lat.Lattice(s.L, s.n, s.Delta, s.V, s.J, s.T, s.seed, encoding=s.encoding)
+        g.sweep(s.sweeps)
+        assert np.array_equal(g.read_state(), done[r.index]["codes"]), r.index
+        assert g.observables().as_dict()["E"] == done[r.index]["obs"]["E"]
+    for k in rng.choice(len(reqs), size=3, replace=False):
+        r = reqs[int(k)]
+        s = r.spec
+        o = _oracle(s)
+        o.sweeps(s.sweeps)
+        assert np.array_equal(o.codes, done[r.index]["codes"]), r.index
+        ob = done[r.index]["obs"]
+        assert [ob["sum_S"], ob["n_charged"], ob["bond_SS"], ob["bond_ss"], ob["M"], ob["M_stag"],
+                ob["C_stag"]] == o.observables().tolist()
+        assert [ob["track_nD"], ob["track_nV"], ob["track_nJ"]] == o.track.tolist()
