@@ -37,44 +37,55 @@ def build(force: bool = True) -> str:
 _lib = None
 
 
+def _configure(L: ctypes.CDLL) -> ctypes.CDLL:
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    i8p = ctypes.POINTER(ctypes.c_int8)
+    d, u64, i32, i64 = ctypes.c_double, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64
+    L.orc_philox.argtypes = [u32p, u32p, u32p]
+    L.orc_philox.restype = None
+    L.orc_threshold.argtypes = [d, d, d, d, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.orc_threshold.restype = ctypes.c_uint32
+    L.orc_charge_target.argtypes = [i32, d, i64, i64p, i64p]
+    L.orc_charge_target.restype = ctypes.c_int
+    L.orc_init.argtypes = [i32, u64, i64, i64, i8p]
+    L.orc_init.restype = ctypes.c_int
+    L.orc_schedule.argtypes = [i32, u64, u64, i32p, i32p, i32p]
+    L.orc_schedule.restype = None
+    L.orc_sweeps.argtypes = [i32, d, d, d, d, u64, u64, u64, i8p, i64p]
+    L.orc_sweeps.restype = ctypes.c_int
+    L.orc_general_steps.argtypes = [i32, d, d, d, d, u64, u64, u64, i8p, i64p]
+    L.orc_general_steps.restype = ctypes.c_int
+    L.orc_observables.argtypes = [i32, i8p, i64p]
+    L.orc_observables.restype = None
+    L.orc_pair_delta.argtypes = [i32, i8p, i64, i64, ctypes.c_int, ctypes.c_int, i64p]
+    L.orc_pair_delta.restype = None
+    L.orc_pair_config.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    L.orc_pair_config.restype = ctypes.c_int
+    L.orc_energy.argtypes = [d, d, d, i64p]
+    L.orc_energy.restype = d
+    L.orc_series.argtypes = [i32, d, d, d, d, u64, u64, u64, u64, i8p, i64p, i64p]
+    L.orc_series.restype = ctypes.c_int
+    L.orc_general_series.argtypes = [i32, d, d, d, d, u64, u64, u64, u64, i8p, i64p, i64p]
+    L.orc_general_series.restype = ctypes.c_int
+    return L
+
+
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
         build(force=False)
-        L = ctypes.CDLL(_LIB_PATH)
-        u32p = ctypes.POINTER(ctypes.c_uint32)
-        i64p = ctypes.POINTER(ctypes.c_int64)
-        i32p = ctypes.POINTER(ctypes.c_int32)
-        i8p = ctypes.POINTER(ctypes.c_int8)
-        d, u64, i32, i64 = ctypes.c_double, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64
-        L.orc_philox.argtypes = [u32p, u32p, u32p]
-        L.orc_philox.restype = None
-        L.orc_threshold.argtypes = [d, d, d, d, ctypes.c_int, ctypes.c_int, ctypes.c_int]
-        L.orc_threshold.restype = ctypes.c_uint32
-        L.orc_charge_target.argtypes = [i32, d, i64, i64p, i64p]
-        L.orc_charge_target.restype = ctypes.c_int
-        L.orc_init.argtypes = [i32, u64, i64, i64, i8p]
-        L.orc_init.restype = ctypes.c_int
-        L.orc_schedule.argtypes = [i32, u64, u64, i32p, i32p, i32p]
-        L.orc_schedule.restype = None
-        L.orc_sweeps.argtypes = [i32, d, d, d, d, u64, u64, u64, i8p, i64p]
-        L.orc_sweeps.restype = ctypes.c_int
-        L.orc_general_steps.argtypes = [i32, d, d, d, d, u64, u64, u64, i8p, i64p]
-        L.orc_general_steps.restype = ctypes.c_int
-        L.orc_observables.argtypes = [i32, i8p, i64p]
-        L.orc_observables.restype = None
-        L.orc_pair_delta.argtypes = [i32, i8p, i64, i64, ctypes.c_int, ctypes.c_int, i64p]
-        L.orc_pair_delta.restype = None
-        L.orc_pair_config.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
-        L.orc_pair_config.restype = ctypes.c_int
-        L.orc_energy.argtypes = [d, d, d, i64p]
-        L.orc_energy.restype = d
-        L.orc_series.argtypes = [i32, d, d, d, d, u64, u64, u64, u64, i8p, i64p, i64p]
-        L.orc_series.restype = ctypes.c_int
-        L.orc_general_series.argtypes = [i32, d, d, d, d, u64, u64, u64, u64, i8p, i64p, i64p]
-        L.orc_general_series.restype = ctypes.c_int
-        _lib = L
+        _lib = _configure(ctypes.CDLL(_LIB_PATH))
     return _lib
+
+
+def use_library(path: str | None):
+    """Test hook for mutation tests: make every call go to the C library at
+    `path` (a deliberately broken copy of oracle.c), or back to the real one
+    with None.  Returns nothing; not thread-safe."""
+    global _lib
+    _lib = None if path is None else _configure(ctypes.CDLL(path))
 
 
 def _p(arr: np.ndarray, ctype):

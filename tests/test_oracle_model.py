@@ -58,6 +58,7 @@ def test_pair_sets_partition_all_sixteen_two_site_states():
     (128, 0.35, 5734, 5734),
     (4, 0.125, 2, 4),
     (4, -0.125, -2, 4),
+    (4, 0.0625, 0, 4),              # nN = 1 halfway between 0 and 2: ties go to the smaller
 ])
 def test_charge_target(L, n, Q, Nc):
     assert oracle.charge_target(L, n) == (Q, Nc)
@@ -281,3 +282,30 @@ def test_resume_is_bit_exact():
     c = oracle.OracleLattice(16, 0.1, 0.25, 0.5, 1.0, 0.8, seed=21, start_sweep=25, codes=b.codes)
     c.sweeps(35)
     assert np.array_equal(a.codes, c.codes)
+
+
+# ---------------------------------------------------------------- observables of known configurations
+def test_observables_of_known_configurations():
+    """Closed forms: the charge checkerboard, the spin Neel state, uniform
+    states and stripes (every bond counted once, 2N bonds)."""
+    L = 8
+    N = L * L
+    x, y = np.meshgrid(np.arange(L), np.arange(L))
+    par = ((x + y) % 2).reshape(-1)
+    checker = np.where(par == 0, 2, 3).astype(np.int8)      # +1 on even sites, -1 on odd
+    assert oracle.observables(L, checker).tolist() == [0, N, -2 * N, 0, 0, 0, N]
+    neel = par.astype(np.int8)                                # sigma = +1 on even, -1 on odd
+    assert oracle.observables(L, neel).tolist() == [0, 0, 0, -2 * N, 0, N, 0]
+    up = np.zeros(N, dtype=np.int8)
+    assert oracle.observables(L, up).tolist() == [0, 0, 0, 2 * N, N, 0, 0]
+    plus = np.full(N, 2, dtype=np.int8)
+    assert oracle.observables(L, plus).tolist() == [N, N, 2 * N, 0, 0, 0, 0]
+    stripes = np.where(y.reshape(-1) % 2 == 0, 0, 1).astype(np.int8)  # rows alternate spin up/down
+    # horizontal bonds aligned (+N), vertical anti-aligned (-N); staggered sum over a row is 0
+    assert oracle.observables(L, stripes).tolist() == [0, 0, 0, 0, 0, 0, 0]
+    one = np.zeros(N, dtype=np.int8)
+    one[3 * L + 5] = 3                                        # one -1 charge at (5,3) in spin-up sea
+    o = oracle.observables(L, one)
+    assert o[0] == -1 and o[1] == 1 and o[2] == 0 and o[3] == 2 * N - 4 and o[4] == N - 1
+    # site (5,3) has x+y even: the staggered spin sum (0 before) loses +1; the staggered charge is -1
+    assert o[5] == -1 and o[6] == -1
