@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="0 skips the served run")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only copy a device buffer of this many MiB 3 times (HBM counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -124,6 +126,18 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if args.calibrate_copy_mib > 0:
+        # A plain device-to-device copy of known size: what FETCH_SIZE and
+        # WRITE_SIZE read for it scales the counters of the phase kernel.
+        n = args.calibrate_copy_mib << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": n, "copies": 3}), flush=True)
+        return
 
     import paper_2301_11735_amd as lat
 

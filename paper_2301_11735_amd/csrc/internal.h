@@ -18,7 +18,7 @@ struct lattice {
     void *d_state = nullptr;
     uint8_t *d_scratch = nullptr;
     hipStream_t stream = nullptr;
-    lat::Tuning2Bit tuning{0, 0, 0};
+    lat::Tuning2Bit tuning{0, 0, 0, 0};
     bool phase_kernels = false;  // big lattice, or forced: one launch per phase
     uint32_t magic = 0;
 };
@@ -35,6 +35,14 @@ int enqueue_lds_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps
 int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream);
 // v = (tracker nD, nV, nJ, sum S, sum S^2, bonds SS, bonds ss, M, M_st, C_st).
 void fill_obs(const lattice *h, const int64_t *v, lat_obs *out);
+
+// Launch-shape autotuner for the batched kernel.  For every (largest L,
+// batch size) it tries each candidate block size on one real call, timed with
+// HIP events on the call's stream, then keeps the fastest per site update.
+// The chain does not depend on the launch shape, so tuning runs real work.
+// LATTICE_BATCH_THREADS=<n> pins the block size instead.
+int batch_threads_for(int max_L, int count, hipStream_t stream, hipEvent_t *start, hipEvent_t *stop, int *slot);
+void batch_threads_done(int slot, double site_updates);
 
 }  // namespace detail
 }  // namespace lat

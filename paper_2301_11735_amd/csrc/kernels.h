@@ -38,6 +38,8 @@ constexpr size_t kScrDevTab = 0;                      // 933 x 8 = 7464
 constexpr size_t kScrTrans = 7680;                    // 96 x 8 = 768
 constexpr size_t kScrTrack = 8448;                    // 3 x int64
 constexpr size_t kScrObs = kScrTrack + 3 * 8;         // 7 x int64
+constexpr size_t kScrErr = kScrObs + 7 * 8;           // uint32 error flags (bit 0: barrier time-out)
+constexpr size_t kScrBarrier = 8576;                  // uint32 phase-barrier counter (+ 4 spare bytes)
 constexpr size_t kScrDesc = 8704;                     // LatDesc
 constexpr size_t kScrBytes = 16384;
 
@@ -81,14 +83,21 @@ struct Tuning2Bit {
     int rows_per_block;
     int blocks_per_cu;
     int waves_hint;  // >= 8: the build limited to 64 VGPRs (8 waves per SIMD)
+    int persistent;  // 1: one cooperative launch per lattice_sweep call (2-bit), 0: a launch per phase
 };
 
 hipError_t launch_phase_int8(const PhaseArgs &a, hipStream_t s);
 hipError_t launch_phase_2bit(const PhaseArgs &a, const Tuning2Bit &t, hipStream_t s);
+// Persistent 2-bit sweeps (one cooperative launch, device-wide barrier per
+// phase); hipErrorNotSupported when co-residency cannot be guaranteed.
+bool persistent_2bit_supported(int L, const Tuning2Bit &t, int *grid, int *rows);
+hipError_t launch_sweeps_2bit(const PhaseArgs &a, const Tuning2Bit &t, uint32_t sweeps, unsigned *counter,
+                              unsigned *err, hipStream_t s);
 hipError_t launch_zero_i64(unsigned long long *p, int n, hipStream_t s);
 hipError_t launch_observables(const void *state, int L, int encoding, unsigned long long *obs, hipStream_t s);
-// Batched kernel; block size and dynamic LDS are sized for the largest L.
-hipError_t launch_sweep_lds(const BatchArgs &a, int max_L, hipStream_t s);
+// Batched kernel; dynamic LDS is sized for the largest L.  threads = block
+// size (a multiple of 64, at most 1024; 0 = min(1024, N/16 of the largest L)).
+hipError_t launch_sweep_lds(const BatchArgs &a, int max_L, int threads, hipStream_t s);
 // desc->next_sweep += sweeps (after host-scheduled phase launches).
 hipError_t launch_advance(LatDesc *desc, uint32_t sweeps, hipStream_t s);
 // Observables of `count` lattices in one launch: out[10*b .. 10*b+9] =

@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 #include "philox.h"
 
@@ -170,6 +172,28 @@ __global__ void __launch_bounds__(256) k_phase_int8(PhaseArgs a)
 // after the block barrier, thread j assembles b-word jb+1 from its own new
 // codes and those of thread j+1 (mod W), and every b-word has one writer.
 
+// Schedule of sweep s (same definition as the host's): r in {1,2,3};
+// phase p has D_p = (r + 4 m_p, 1 + 2 k_p).
+__device__ __forceinline__ void device_schedule(int L, uint32_t k0, uint32_t k1, uint64_t s, int &r, int (&m)[4],
+                                                int (&k)[4])
+{
+    uint32_t Wd[12];
+#pragma unroll
+    for (uint32_t t = 0; t < 3; ++t) {
+        const u32x4 w = philox4x32_10((uint32_t)s, kDomSchedule, t, (uint32_t)(s >> 32), k0, k1);
+        Wd[4 * t] = w.x;
+        Wd[4 * t + 1] = w.y;
+        Wd[4 * t + 2] = w.z;
+        Wd[4 * t + 3] = w.w;
+    }
+    r = 1 + (int)(((Wd[0] >> 8) * 3u) >> 24);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        m[p] = (int)mulhi_u32(Wd[1 + 2 * p], (uint32_t)(L / 4));
+        k[p] = (int)mulhi_u32(Wd[2 + 2 * p], (uint32_t)(L / 2));
+    }
+}
+
 // 16 sites of the class row at word offset `row` of `st`, starting at class
 // position xs (periodic).  32-bit offsets keep the base pointer uniform.
 __device__ __forceinline__ uint32_t load16(const uint32_t *__restrict__ st, uint32_t row, int W, int xs)
@@ -227,12 +251,11 @@ struct PairWords {
     uint32_t A0, AL, AR, AU, AD, B0, BL, BR, BU, BD;
 };
 
-template <int MinWaves>
-__global__ void __launch_bounds__(1024, MinWaves) k_phase_2bit(PhaseArgs a, int rows_per_block)
+// One phase of the 2-bit lattice by this block: row groups blockIdx.x,
+// blockIdx.x + gridDim.x, ...  The tables are already staged in LDS.
+__device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_block, const uint2 *__restrict__ s_tab,
+                                           const uint2 *__restrict__ s_trans, uint32_t *xch, int (&tr)[3])
 {
-    __shared__ uint2 s_tab[kDevTabEntries];
-    __shared__ uint2 s_trans[kTransEntries];
-    extern __shared__ uint32_t xch[];  // 2 x blockDim (double buffered)
 
     const int L = a.L, W = L >> 6, H = L >> 1, Lq = L >> 2;
     const int rr = threadIdx.x / W, j = threadIdx.x - rr * W;
@@ -283,16 +306,12 @@ __global__ void __launch_bounds__(1024, MinWaves) k_phase_2bit(PhaseArgs a, int 
         return w;
     };
 
-    // The first group's words are in flight while the tables are staged; each
-    // later group's words are fetched before the current group is computed.
+    // Each group's words are fetched before the previous group is computed.
     // Every word read is either never written in this phase or written only
     // by this block in the iteration that owns it, after its read.
     int g = blockIdx.x;
     PairWords cur{};
     if (g < n_groups) cur = load_words(g);
-    stage_tables(s_tab, s_trans, a.dev_tab, a.trans);
-
-    int tr[3] = {0, 0, 0};
     int buf = 0;
     for (; g < n_groups; g += gridDim.x, buf ^= 1) {
         const int gn = g + gridDim.x;
@@ -346,8 +365,82 @@ __global__ void __launch_bounds__(1024, MinWaves) k_phase_2bit(PhaseArgs a, int 
         st[oB0 + (uint32_t)Yb * W + jw_out] = word;
         cur = nxt;
     }
+    __syncthreads();  // the exchange buffer is reused by the next phase
+}
+
+template <int MinWaves>
+__global__ void __launch_bounds__(1024, MinWaves) k_phase_2bit(PhaseArgs a, int rows_per_block)
+{
+    __shared__ uint2 s_tab[kDevTabEntries];
+    __shared__ uint2 s_trans[kTransEntries];
+    extern __shared__ uint32_t xch[];  // 2 x blockDim (double buffered)
+    stage_tables(s_tab, s_trans, a.dev_tab, a.trans);
+    int tr[3] = {0, 0, 0};
+    phase_2bit(a, rows_per_block, s_tab, s_trans, xch, tr);
     block_reduce_add<3>(tr, a.track);
 }
+
+// Device-wide barrier between phases of the persistent kernel: every block
+// arrives once per phase on a monotonic counter.  Release: the fence writes
+// this block's results back past the compute unit's caches before the
+// arrival; acquire: the fence after the wait invalidates them.  The wait is
+// bounded: after about 2^24 polls the block raises the error flag and goes
+// on (results are then invalid and reported as an error), so no wave can
+// spin forever.
+__device__ __forceinline__ void grid_barrier(unsigned *counter, unsigned target, unsigned *err)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(counter, 1u);
+        unsigned polls = 0;
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++polls > (1u << 24)) {
+                atomicOr(err, 1u);
+                break;
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// Persistent form: `sweeps` sweeps from sweep a.s_lo|a.s_hi in one launch of
+// co-resident blocks (cooperative launch), tables staged once, schedules
+// computed on the device, a device-wide barrier after every phase.
+template <int MinWaves>
+__global__ void __launch_bounds__(1024, MinWaves) k_sweeps_2bit(PhaseArgs a, int rows_per_block, uint32_t sweeps,
+                                                                unsigned *counter, unsigned *err)
+{
+    __shared__ uint2 s_tab[kDevTabEntries];
+    __shared__ uint2 s_trans[kTransEntries];
+    extern __shared__ uint32_t xch[];
+    stage_tables(s_tab, s_trans, a.dev_tab, a.trans);
+    int tr[3] = {0, 0, 0};
+    const uint64_t s0 = ((uint64_t)a.s_hi << 32) | a.s_lo;
+    unsigned arrivals = 0;
+    for (uint32_t i = 0; i < sweeps; ++i) {
+        const uint64_t s = s0 + i;
+        int r, mm[4], kk[4];
+        device_schedule(a.L, a.key0, a.key1, s, r, mm, kk);
+        PhaseArgs b = a;
+        b.s_lo = (uint32_t)s;
+        b.s_hi = (uint32_t)(s >> 32);
+        b.r = r;
+        for (int p = 0; p < 4; ++p) {
+            b.p = p;
+            b.m = mm[p];
+            b.k = kk[p];
+            phase_2bit(b, rows_per_block, s_tab, s_trans, xch, tr);
+            arrivals += gridDim.x;
+            grid_barrier(counter, arrivals, err);
+        }
+    }
+    block_reduce_add<3>(tr, a.track);
+}
+
+
 
 // ---------------------------------------------------------------------------
 __global__ void k_zero_i64(unsigned long long *p, int n)
@@ -439,28 +532,6 @@ __global__ void __launch_bounds__(256) k_obs_2bit(const uint32_t *__restrict__ s
 // fields of, so the new codes are merged with LDS atomic xor; every read of
 // an updated word extracts only the reader's own field, which nobody else
 // writes, and neighbour words are never written in the phase.
-
-// Schedule of sweep s (same definition as the host's): r in {1,2,3};
-// phase p has D_p = (r + 4 m_p, 1 + 2 k_p).
-__device__ __forceinline__ void device_schedule(int L, uint32_t k0, uint32_t k1, uint64_t s, int &r, int (&m)[4],
-                                                int (&k)[4])
-{
-    uint32_t Wd[12];
-#pragma unroll
-    for (uint32_t t = 0; t < 3; ++t) {
-        const u32x4 w = philox4x32_10((uint32_t)s, kDomSchedule, t, (uint32_t)(s >> 32), k0, k1);
-        Wd[4 * t] = w.x;
-        Wd[4 * t + 1] = w.y;
-        Wd[4 * t + 2] = w.z;
-        Wd[4 * t + 3] = w.w;
-    }
-    r = 1 + (int)(((Wd[0] >> 8) * 3u) >> 24);
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        m[p] = (int)mulhi_u32(Wd[1 + 2 * p], (uint32_t)(L / 4));
-        k[p] = (int)mulhi_u32(Wd[2 + 2 * p], (uint32_t)(L / 2));
-    }
-}
 
 struct LdsGeom {
     int L, Lq, H, Wp;
@@ -699,6 +770,39 @@ hipError_t launch_phase_2bit(const PhaseArgs &a, const Tuning2Bit &t, hipStream_
     return hipGetLastError();
 }
 
+bool persistent_2bit_supported(int L, const Tuning2Bit &t, int *grid_out, int *rows_out)
+{
+    int dev = 0, coop = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return false;
+    const int W = L >> 6, R = rows_per_block_2bit(W, t.rows_per_block), block = R * W;
+    int per_cu = 0;
+    const void *fn = t.waves_hint >= 8 ? (const void *)k_sweeps_2bit<8> : (const void *)k_sweeps_2bit<1>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, (size_t)block * 8u) != hipSuccess ||
+        per_cu < 1)
+        return false;
+    const int want = t.blocks_per_cu > 0 ? t.blocks_per_cu : 1;
+    *grid_out = std::min(per_cu, want) * num_cus();
+    *rows_out = R;
+    return true;
+}
+
+hipError_t launch_sweeps_2bit(const PhaseArgs &a, const Tuning2Bit &t, uint32_t sweeps, unsigned *counter,
+                              unsigned *err, hipStream_t s)
+{
+    int grid = 0, R = 0;
+    if (!persistent_2bit_supported(a.L, t, &grid, &R)) return hipErrorNotSupported;
+    const int block = R * (a.L >> 6);
+    hipError_t e = launch_zero_i64((unsigned long long *)counter, 1, s);  // counter (and the word after it)
+    if (e != hipSuccess) return e;
+    PhaseArgs args = a;
+    int rows = R;
+    uint32_t n = sweeps;
+    void *kargs[] = {&args, &rows, &n, &counter, &err};
+    const void *fn = t.waves_hint >= 8 ? (const void *)k_sweeps_2bit<8> : (const void *)k_sweeps_2bit<1>;
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), kargs, (size_t)block * 8u, s);
+}
+
 hipError_t launch_zero_i64(unsigned long long *p, int n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_zero_i64, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
@@ -720,10 +824,11 @@ hipError_t launch_observables(const void *state, int L, int encoding, unsigned l
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_lds(const BatchArgs &a, int max_L, hipStream_t s)
+hipError_t launch_sweep_lds(const BatchArgs &a, int max_L, int threads, hipStream_t s)
 {
     const uint32_t calls = (uint32_t)max_L * (uint32_t)max_L / 16u;
     uint32_t block = calls < 1024u ? ((calls + 63u) / 64u) * 64u : 1024u;
+    if (threads > 0) block = (uint32_t)std::min(1024, std::max(64, threads / 64 * 64));
     if (block < 64u) block = 64u;
     const size_t lds = lds_state_words(max_L) * 4u;
     static bool attr_set = false;

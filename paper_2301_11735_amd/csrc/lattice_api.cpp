@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -222,10 +224,11 @@ void build_transition_table(std::vector<uint32_t> &trans)
 
 Tuning2Bit tuning_from_env()
 {
-    Tuning2Bit t{0, 0, 0};
+    Tuning2Bit t{0, 0, 0, 0};
     if (const char *v = std::getenv("LATTICE_2BIT_ROWS")) t.rows_per_block = std::atoi(v);
     if (const char *v = std::getenv("LATTICE_2BIT_BLOCKS_PER_CU")) t.blocks_per_cu = std::atoi(v);
     if (const char *v = std::getenv("LATTICE_2BIT_WAVES")) t.waves_hint = std::atoi(v);
+    if (const char *v = std::getenv("LATTICE_PERSISTENT")) t.persistent = std::atoi(v);
     return t;
 }
 
@@ -307,7 +310,23 @@ int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
     a.L = h->L;
     a.key0 = (uint32_t)h->seed;
     a.key1 = (uint32_t)(h->seed >> 32);
-    for (uint32_t i = 0; i < sweeps; ++i) {
+    uint32_t left = sweeps;
+    if (h->enc == LAT_ENC_2BIT && h->tuning.persistent) {
+        // one cooperative launch per chunk; the barrier counter stays far below 2^32
+        constexpr uint32_t kChunk = 65536;
+        while (left > 0) {
+            const uint32_t n = std::min(left, kChunk);
+            const uint64_t s = h->start_sweep + h->done + (sweeps - left);
+            a.s_lo = (uint32_t)s;
+            a.s_hi = (uint32_t)(s >> 32);
+            const hipError_t e = launch_sweeps_2bit(a, h->tuning, n, (unsigned *)(h->d_scratch + kScrBarrier),
+                                                    (unsigned *)(h->d_scratch + kScrErr), stream);
+            if (e == hipErrorNotSupported) break;  // no co-residency guarantee: per-phase launches below
+            if (e != hipSuccess) return hip_fail(e, "persistent sweep launch");
+            left -= n;
+        }
+    }
+    for (uint32_t i = sweeps - left; i < sweeps; ++i) {
         const uint64_t s = h->start_sweep + h->done + i;
         const Schedule sc = sweep_schedule(h->L, h->seed, s);
         a.s_lo = (uint32_t)s;
@@ -330,6 +349,85 @@ int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
     return LAT_OK;
 }
 
+// ---- autotuner for the batched kernel's block size ----
+namespace {
+
+struct TuneEntry {
+    std::vector<int> candidates;
+    std::vector<double> ns_per_update;  // < 0: not measured yet
+    int pending = -1;                   // candidate being timed by the current launch
+    hipEvent_t start = nullptr, stop = nullptr;
+    int best = -1;
+};
+
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, TuneEntry> g_tune;
+std::vector<std::pair<int, int>> g_tune_slots;
+
+int pinned_batch_threads()
+{
+    const char *v = std::getenv("LATTICE_BATCH_THREADS");
+    return v ? std::atoi(v) : 0;
+}
+
+}  // namespace
+
+// Returns the block size to use (0 = default) and, while tuning, events to
+// record around the launch plus a slot for batch_threads_done, which waits
+// for that launch (the first calls for a new shape are therefore blocking).
+int batch_threads_for(int max_L, int count, hipStream_t stream, hipEvent_t *start, hipEvent_t *stop, int *slot)
+{
+    (void)stream;
+    *start = *stop = nullptr;
+    *slot = -1;
+    if (const int pinned = pinned_batch_threads()) return pinned;
+    const int calls = max_L * max_L / 16;
+    int bucket = 1;
+    while (bucket < count) bucket *= 2;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto key = std::make_pair(max_L, bucket);
+    TuneEntry &t = g_tune[key];
+    if (t.candidates.empty()) {
+        for (int c : {1024, 512, 256})
+            if (c <= 1024 && (c / 2 < calls || c == 256)) t.candidates.push_back(c);
+        t.ns_per_update.assign(t.candidates.size(), -1.0);
+    }
+    if (t.best >= 0) return t.candidates[t.best];
+    for (size_t i = 0; i < t.candidates.size(); ++i) {
+        if (t.ns_per_update[i] < 0) {
+            if (!t.start) {
+                if (hipEventCreate(&t.start) != hipSuccess || hipEventCreate(&t.stop) != hipSuccess) return 0;
+            }
+            t.pending = (int)i;
+            *start = t.start;
+            *stop = t.stop;
+            g_tune_slots.push_back(key);
+            *slot = (int)g_tune_slots.size() - 1;
+            return t.candidates[i];
+        }
+    }
+    return 0;
+}
+
+void batch_threads_done(int slot, double site_updates)
+{
+    if (slot < 0) return;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    TuneEntry &t = g_tune[g_tune_slots[(size_t)slot]];
+    if (t.pending < 0) return;
+    float ms = 0.f;
+    if (hipEventSynchronize(t.stop) != hipSuccess || hipEventElapsedTime(&ms, t.start, t.stop) != hipSuccess) return;
+    t.ns_per_update[t.pending] = site_updates > 0 ? (double)ms * 1e6 / site_updates : 0.0;
+    t.pending = -1;
+    bool all = true;
+    for (double v : t.ns_per_update) all = all && v >= 0;
+    if (all) {
+        t.best = 0;
+        for (size_t i = 1; i < t.ns_per_update.size(); ++i)
+            if (t.ns_per_update[i] < t.ns_per_update[(size_t)t.best]) t.best = (int)i;
+    }
+}
+
 // Batched path: lattices resident in LDS, up to kMaxBatch per launch.
 int enqueue_lds_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps, uint32_t uniform,
                        hipStream_t stream)
@@ -338,13 +436,23 @@ int enqueue_lds_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps
         BatchArgs a{};
         a.count = std::min<int32_t>(kMaxBatch, count - b);
         int max_L = 0;
+        double updates = 0;
         for (int i = 0; i < a.count; ++i) {
             a.scratch[i] = hs[b + i]->d_scratch;
             a.sweeps[i] = sweeps ? sweeps[b + i] : uniform;
             max_L = std::max(max_L, hs[b + i]->L);
+            updates += (double)hs[b + i]->N * a.sweeps[i];
         }
-        const hipError_t e = launch_sweep_lds(a, max_L, stream);
+        hipEvent_t t0, t1;
+        int slot;
+        const int threads = batch_threads_for(max_L, a.count, stream, &t0, &t1, &slot);
+        if (t0) (void)hipEventRecord(t0, stream);
+        const hipError_t e = launch_sweep_lds(a, max_L, threads, stream);
         if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
+        if (t1) {
+            (void)hipEventRecord(t1, stream);
+            batch_threads_done(slot, updates);
+        }
         for (int i = 0; i < a.count; ++i) hs[b + i]->done += a.sweeps[i];
     }
     return LAT_OK;
@@ -482,7 +590,7 @@ int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void 
         e = hipMemcpyAsync(h->d_scratch + kScrTrans, trans.data(), trans.size() * 4, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->d_scratch + kScrDesc, &desc, sizeof(desc), hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess) e = launch_zero_i64((unsigned long long *)(h->d_scratch + kScrTrack), 10, h->stream);
+    if (e == hipSuccess) e = launch_zero_i64((unsigned long long *)(h->d_scratch + kScrTrack), 11, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // host staging buffers die with this frame
     if (e != hipSuccess) {
         h->magic = 0;
@@ -555,10 +663,11 @@ int lattice_observables(lattice *h, lat_obs *out)
     unsigned long long *track = (unsigned long long *)(h->d_scratch + kScrTrack);
     unsigned long long *obs = (unsigned long long *)(h->d_scratch + kScrObs);
     hipError_t e = launch_observables(h->d_state, h->L, h->enc, obs, h->stream);
-    int64_t v[10];
+    int64_t v[11];  // tracker, 7 sums, error flags
     if (e == hipSuccess) e = hipMemcpyAsync(v, track, sizeof(v), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "lattice_observables");
+    if ((uint32_t)v[10] & 1u) return fail(LAT_EHIP, "a device-wide phase barrier timed out; the state is invalid");
     fill_obs(h, v, out);
     return LAT_OK;
 }

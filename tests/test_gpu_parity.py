@@ -289,3 +289,14 @@ def test_served_results_equal_alone_and_oracle():
         assert [ob["sum_S"], ob["n_charged"], ob["bond_SS"], ob["bond_ss"], ob["M"], ob["M_stag"],
                 ob["C_stag"]] == o.observables().tolist()
         assert [ob["track_nD"], ob["track_nV"], ob["track_nJ"]] == o.track.tolist()
+
+
+@pytest.mark.parametrize("spec", [
+    SMALL.with_(L=576, encoding=1, seed=81),                     # 9 words per class row
+    SMALL.with_(L=1024, encoding=1, T=0.6, n=-0.15, seed=82),
+], ids=lambda s: f"L{s.L}")
+def test_persistent_path_matches_oracle(spec, monkeypatch):
+    """2-bit lattices above the LDS size with all sweeps of a call in one
+    cooperative launch (device-wide barrier between phases)."""
+    monkeypatch.setenv("LATTICE_PERSISTENT", "1")
+    _run_parity(spec, [1, 3, 8])
