@@ -41,6 +41,34 @@ ALU_OPS_PER_SITE_UPDATE = 10.0
 BYTES_PER_SITE_UPDATE_2BIT = 0.5
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_phase_2bit_L8192_traffic.txt")
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+
+    path = os.path.join(ROOT, "paper_2301_11735_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per phase launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None if it was taken on another kernel source."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_SUMMARY):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernels_hip_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,7 +234,7 @@ def main():
             "peak": VALU_PEAK_OPS / 1e12,
             "unit": "Tops/s",
             "frac": alu_achieved / VALU_PEAK_OPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "kernel": "k_phase_2bit",
             "avg_launch_us": phase_us,
         },

@@ -32,16 +32,22 @@ constexpr int kDevTabEntries = kDevJLine + 33; // 933 x uint2
 // C chosen so that dot4(coef, sums) + C is the move's device-table index.
 constexpr int kTransEntries = 16 * 6;
 
-// Scratch buffer layout (bytes).  Tracker (3 int64) and observable sums
-// (7 int64) are adjacent so one 80-byte copy returns both.
+// Scratch buffer layout (bytes).  The tracker total (3 int64), observable
+// sums (7 int64) and error flags are adjacent so one 88-byte copy returns all.
+// Energy-tracker contributions are accumulated without contention: the phase
+// kernels add block b's sums into slot b (kMaxSlots slots), single-block
+// kernels into the base triple; k_sum_tracker folds them into the total.
 constexpr size_t kScrDevTab = 0;                      // 933 x 8 = 7464
 constexpr size_t kScrTrans = 7680;                    // 96 x 8 = 768
-constexpr size_t kScrTrack = 8448;                    // 3 x int64
+constexpr size_t kScrTrack = 8448;                    // 3 x int64: tracker total (output)
 constexpr size_t kScrObs = kScrTrack + 3 * 8;         // 7 x int64
 constexpr size_t kScrErr = kScrObs + 7 * 8;           // uint32 error flags (bit 0: barrier time-out)
 constexpr size_t kScrBarrier = 8576;                  // uint32 phase-barrier counter (+ 4 spare bytes)
 constexpr size_t kScrDesc = 8704;                     // LatDesc
-constexpr size_t kScrBytes = 16384;
+constexpr size_t kScrTrackBase = 8768;                // 3 x int64 from single-block kernels
+constexpr size_t kScrSlots = 16384;                   // kMaxSlots x 3 x int64 from the phase kernels
+constexpr int kMaxSlots = 1024;
+constexpr size_t kScrBytes = kScrSlots + (size_t)kMaxSlots * 24;  // 40960
 
 // Per-lattice descriptor kept in the lattice's scratch, read by the batched
 // kernel.  next_sweep is advanced on the device by every path that sweeps.
@@ -70,7 +76,7 @@ struct PhaseArgs {
     void *state;
     const uint2 *dev_tab;    // kDevTabEntries
     const uint2 *trans;      // kTransEntries
-    unsigned long long *track;  // 3 x int64 (two's complement) accumulators
+    unsigned long long *track;  // tracker slots: block b adds its 3 sums at track[3b..3b+2]
     int L;
     int p, r, m, k;
     uint32_t key0, key1;
@@ -94,6 +100,8 @@ bool persistent_2bit_supported(int L, const Tuning2Bit &t, int *grid, int *rows)
 hipError_t launch_sweeps_2bit(const PhaseArgs &a, const Tuning2Bit &t, uint32_t sweeps, unsigned *counter,
                               unsigned *err, hipStream_t s);
 hipError_t launch_zero_i64(unsigned long long *p, int n, hipStream_t s);
+// Tracker total = base triple + all slots, written at scratch + kScrTrack.
+hipError_t launch_sum_tracker(uint8_t *scratch, hipStream_t s);
 hipError_t launch_observables(const void *state, int L, int encoding, unsigned long long *obs, hipStream_t s);
 // Batched kernel; dynamic LDS is sized for the largest L.  threads = block
 // size (a multiple of 64, at most 1024; 0 = min(1024, N/16 of the largest L)).

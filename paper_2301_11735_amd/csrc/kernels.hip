@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(256) k_phase_int8(PhaseArgs a)
         }
         unpack_tracker(packed, tr);
     }
-    block_reduce_add<3>(tr, a.track);
+    block_reduce_add<3>(tr, a.track + 3 * (size_t)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -377,7 +377,7 @@ __global__ void __launch_bounds__(1024, MinWaves) k_phase_2bit(PhaseArgs a, int 
     stage_tables(s_tab, s_trans, a.dev_tab, a.trans);
     int tr[3] = {0, 0, 0};
     phase_2bit(a, rows_per_block, s_tab, s_trans, xch, tr);
-    block_reduce_add<3>(tr, a.track);
+    block_reduce_add<3>(tr, a.track + 3 * (size_t)blockIdx.x);
 }
 
 // Device-wide barrier between phases of the persistent kernel: every block
@@ -437,7 +437,7 @@ __global__ void __launch_bounds__(1024, MinWaves) k_sweeps_2bit(PhaseArgs a, int
             grid_barrier(counter, arrivals, err);
         }
     }
-    block_reduce_add<3>(tr, a.track);
+    block_reduce_add<3>(tr, a.track + 3 * (size_t)blockIdx.x);
 }
 
 
@@ -645,7 +645,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(BatchArgs args)
         }
     }
     if (threadIdx.x == 0) ((LatDesc *)(scr + kScrDesc))->next_sweep = d.next_sweep + my_sweeps;
-    block_reduce_add<3>(tr, (unsigned long long *)(scr + kScrTrack));
+    block_reduce_add<3>(tr, (unsigned long long *)(scr + kScrTrackBase));
 }
 
 __global__ void k_advance(LatDesc *desc, uint32_t sweeps)
@@ -711,7 +711,42 @@ __global__ void __launch_bounds__(256) k_obs_batch(BatchArgs args, unsigned long
     if (threadIdx.x < 10) o[threadIdx.x] = 0ull;
     __syncthreads();
     block_reduce_add<7>(v, o + 3);
-    if (threadIdx.x < 3) o[threadIdx.x] = ((const unsigned long long *)(scr + kScrTrack))[threadIdx.x];
+    long long t3[3] = {0, 0, 0};
+    const long long *slots = (const long long *)(scr + kScrSlots);
+    for (int i = threadIdx.x; i < kMaxSlots; i += blockDim.x) {
+        t3[0] += slots[3 * i];
+        t3[1] += slots[3 * i + 1];
+        t3[2] += slots[3 * i + 2];
+    }
+    if (threadIdx.x == 0) {
+        const long long *base = (const long long *)(scr + kScrTrackBase);
+        t3[0] += base[0];
+        t3[1] += base[1];
+        t3[2] += base[2];
+    }
+    block_reduce_add<3>(t3, o);
+}
+
+// Tracker total of one lattice: base triple plus every per-block slot.
+__global__ void __launch_bounds__(256) k_sum_tracker(uint8_t *scr)
+{
+    long long t3[3] = {0, 0, 0};
+    const long long *slots = (const long long *)(scr + kScrSlots);
+    for (int i = threadIdx.x; i < kMaxSlots; i += blockDim.x) {
+        t3[0] += slots[3 * i];
+        t3[1] += slots[3 * i + 1];
+        t3[2] += slots[3 * i + 2];
+    }
+    if (threadIdx.x == 0) {
+        const long long *base = (const long long *)(scr + kScrTrackBase);
+        t3[0] += base[0];
+        t3[1] += base[1];
+        t3[2] += base[2];
+    }
+    unsigned long long *out = (unsigned long long *)(scr + kScrTrack);
+    if (threadIdx.x < 3) out[threadIdx.x] = 0ull;
+    __syncthreads();
+    block_reduce_add<3>(t3, out);
 }
 
 int g_num_cus = 0;
@@ -737,7 +772,8 @@ hipError_t launch_phase_int8(const PhaseArgs &a, hipStream_t s)
     const uint32_t n_calls = (uint32_t)a.L * (uint32_t)a.L / 16u;
     const uint32_t block = 256;
     uint32_t grid = (n_calls + block - 1) / block;
-    const uint32_t cap = 4u * (uint32_t)num_cus();
+    uint32_t cap = 4u * (uint32_t)num_cus();
+    if (cap > (uint32_t)kMaxSlots) cap = (uint32_t)kMaxSlots;
     if (grid > cap) grid = cap;
     hipLaunchKernelGGL(k_phase_int8, dim3(grid), dim3(block), 0, s, a);
     return hipGetLastError();
@@ -763,6 +799,7 @@ hipError_t launch_phase_2bit(const PhaseArgs &a, const Tuning2Bit &t, hipStream_
     int grid = H / R;
     const int bpc = t.blocks_per_cu > 0 ? t.blocks_per_cu : 1;
     if (grid > bpc * num_cus()) grid = bpc * num_cus();
+    if (grid > kMaxSlots) grid = kMaxSlots;
     if (t.waves_hint >= 8)
         hipLaunchKernelGGL(k_phase_2bit<8>, dim3(grid), dim3(block), (size_t)block * 8u, s, a, R);
     else
@@ -782,7 +819,7 @@ bool persistent_2bit_supported(int L, const Tuning2Bit &t, int *grid_out, int *r
         per_cu < 1)
         return false;
     const int want = t.blocks_per_cu > 0 ? t.blocks_per_cu : 1;
-    *grid_out = std::min(per_cu, want) * num_cus();
+    *grid_out = std::min(std::min(per_cu, want) * num_cus(), kMaxSlots);
     *rows_out = R;
     return true;
 }
@@ -801,6 +838,12 @@ hipError_t launch_sweeps_2bit(const PhaseArgs &a, const Tuning2Bit &t, uint32_t 
     void *kargs[] = {&args, &rows, &n, &counter, &err};
     const void *fn = t.waves_hint >= 8 ? (const void *)k_sweeps_2bit<8> : (const void *)k_sweeps_2bit<1>;
     return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), kargs, (size_t)block * 8u, s);
+}
+
+hipError_t launch_sum_tracker(uint8_t *scratch, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_tracker, dim3(1), dim3(256), 0, s, scratch);
+    return hipGetLastError();
 }
 
 hipError_t launch_zero_i64(unsigned long long *p, int n, hipStream_t s)

@@ -306,7 +306,7 @@ int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
     a.state = h->d_state;
     a.dev_tab = (const uint2 *)(h->d_scratch + kScrDevTab);
     a.trans = (const uint2 *)(h->d_scratch + kScrTrans);
-    a.track = (unsigned long long *)(h->d_scratch + kScrTrack);
+    a.track = (unsigned long long *)(h->d_scratch + kScrSlots);
     a.L = h->L;
     a.key0 = (uint32_t)h->seed;
     a.key1 = (uint32_t)(h->seed >> 32);
@@ -591,6 +591,8 @@ int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void 
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->d_scratch + kScrDesc, &desc, sizeof(desc), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = launch_zero_i64((unsigned long long *)(h->d_scratch + kScrTrack), 11, h->stream);
+    if (e == hipSuccess) e = launch_zero_i64((unsigned long long *)(h->d_scratch + kScrTrackBase), 3, h->stream);
+    if (e == hipSuccess) e = launch_zero_i64((unsigned long long *)(h->d_scratch + kScrSlots), 3 * kMaxSlots, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // host staging buffers die with this frame
     if (e != hipSuccess) {
         h->magic = 0;
@@ -663,6 +665,7 @@ int lattice_observables(lattice *h, lat_obs *out)
     unsigned long long *track = (unsigned long long *)(h->d_scratch + kScrTrack);
     unsigned long long *obs = (unsigned long long *)(h->d_scratch + kScrObs);
     hipError_t e = launch_observables(h->d_state, h->L, h->enc, obs, h->stream);
+    if (e == hipSuccess) e = launch_sum_tracker(h->d_scratch, h->stream);
     int64_t v[11];  // tracker, 7 sums, error flags
     if (e == hipSuccess) e = hipMemcpyAsync(v, track, sizeof(v), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);

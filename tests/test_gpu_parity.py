@@ -300,3 +300,18 @@ def test_persistent_path_matches_oracle(spec, monkeypatch):
     cooperative launch (device-wide barrier between phases)."""
     monkeypatch.setenv("LATTICE_PERSISTENT", "1")
     _run_parity(spec, [1, 3, 8])
+
+
+def test_autotuned_batch_launch_shapes_match_oracle():
+    """The first calls for a new batch shape each try another block size
+    (1024, 512, 256 threads per lattice) before the fastest is kept; every
+    call must leave every lattice bit-exact."""
+    _say("case autotuned batch shapes")
+    specs = [SMALL.with_(L=L, encoding=1, seed=900 + i, T=0.4 + 0.2 * i) for i, L in enumerate([192, 192, 128, 64, 192])]
+    gs = [_make(s) for s in specs]
+    os_ = [_oracle(s) for s in specs]
+    for call, k in enumerate([3, 2, 4, 3, 2]):
+        lat.sweep_batch(gs, k)
+        for s, g, o in zip(specs, gs, os_):
+            o.sweeps(k)
+            assert np.array_equal(g.read_state(), o.codes), f"call {call} L={s.L}"
