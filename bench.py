@@ -69,6 +69,50 @@ def measured_traffic():
         return None
 
 
+def _counter_rows(path):
+    import csv
+
+    return [(r["Kernel_Name"], float(r["Counter_Value"])) for r in csv.DictReader(open(path))]
+
+
+def write_traffic_summary(fetch_csv, write_csv, cfetch_csv, cwrite_csv, out=TRAFFIC_SUMMARY):
+    """Scale the phase kernel's FETCH_SIZE / WRITE_SIZE (KiB-like units per
+    dispatch) by what the same counters read for a device copy of a known
+    size, and write bytes per launch with the digest of the kernel source."""
+    import statistics
+
+    copy_bytes = 256 << 20
+
+    def per_dispatch(path, name):
+        return [v for k, v in _counter_rows(path) if name in k]
+
+    def copy_factor(path):
+        # the three largest copyBuffer dispatches are the 256 MiB copies
+        vals = sorted(per_dispatch(path, "copyBuffer"))[-3:]
+        return copy_bytes / statistics.median(vals)
+
+    f = per_dispatch(fetch_csv, "k_phase_2bit")
+    w = per_dispatch(write_csv, "k_phase_2bit")
+    ff, fw = copy_factor(cfetch_csv), copy_factor(cwrite_csv)
+    fetch_b, write_b = statistics.mean(f) * ff, statistics.mean(w) * fw
+    lines = [
+        "# HBM-side traffic of k_phase_2bit at L=8192 (one phase launch updates N/4 = 16.8M sites)",
+        "# counters: rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE, one pass each, on",
+        "#   python3 bench.py --steps 4 --warmup 1 --no-cpu-baseline --no-batched --serve-seconds 0",
+        "# calibration: the same counters on python3 bench.py --calibrate-copy-mib 256 (a 268435456-byte",
+        "#   device copy reads and writes that many bytes); factor = bytes / counter value",
+        "# written by: python3 bench.py --traffic-summary <fetch csv> <write csv> <copy fetch csv> <copy write csv>",
+        f"# phase dispatches: fetch {len(f)}, write {len(w)}",
+        f"# FETCH_SIZE mean {statistics.mean(f):.1f} min {min(f):.1f} max {max(f):.1f}; copy factor {ff:.4f}",
+        f"# WRITE_SIZE mean {statistics.mean(w):.1f} min {min(w):.1f} max {max(w):.1f}; copy factor {fw:.4f}",
+        f"kernels_hip_sha256={kernel_source_digest()}",
+        f"fetch_bytes_per_launch={fetch_b:.0f}",
+        f"write_bytes_per_launch={write_b:.0f}",
+    ]
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +124,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="0 skips the served run")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only copy a device buffer of this many MiB 3 times (HBM counter calibration) and exit")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write the traffic summary from four rocprofv3 --pmc counter_collection.csv files and exit")
     return ap.parse_args()
 
 
@@ -149,6 +195,9 @@ def served_run(seconds: float) -> dict:
 
 def main():
     args = parse()
+    if args.traffic_summary:
+        write_traffic_summary(*args.traffic_summary)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (run with --gpus 1)",
               file=sys.stderr)

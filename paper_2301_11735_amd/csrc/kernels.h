@@ -34,20 +34,23 @@ constexpr int kTransEntries = 16 * 6;
 
 // Scratch buffer layout (bytes).  The tracker total (3 int64), observable
 // sums (7 int64) and error flags are adjacent so one 88-byte copy returns all.
-// Energy-tracker contributions are accumulated without contention: the phase
-// kernels add block b's sums into slot b (kMaxSlots slots), single-block
-// kernels into the base triple; k_sum_tracker folds them into the total.
+// Partial sums are gathered without contended atomics: the phase kernels add
+// block b's tracker sums into tracker slot b, the observable reduction writes
+// block b's sums into observable slot b, single-block kernels add into the
+// tracker base; k_fold_sums folds slots into the totals.
 constexpr size_t kScrDevTab = 0;                      // 933 x 8 = 7464
 constexpr size_t kScrTrans = 7680;                    // 96 x 8 = 768
 constexpr size_t kScrTrack = 8448;                    // 3 x int64: tracker total (output)
-constexpr size_t kScrObs = kScrTrack + 3 * 8;         // 7 x int64
+constexpr size_t kScrObs = kScrTrack + 3 * 8;         // 7 x int64: observable sums (output)
 constexpr size_t kScrErr = kScrObs + 7 * 8;           // uint32 error flags (bit 0: barrier time-out)
 constexpr size_t kScrBarrier = 8576;                  // uint32 phase-barrier counter (+ 4 spare bytes)
 constexpr size_t kScrDesc = 8704;                     // LatDesc
 constexpr size_t kScrTrackBase = 8768;                // 3 x int64 from single-block kernels
-constexpr size_t kScrSlots = 16384;                   // kMaxSlots x 3 x int64 from the phase kernels
+constexpr size_t kScrObsSlots = 9216;                 // kMaxObsSlots x 7 x int64
+constexpr int kMaxObsSlots = 256;
+constexpr size_t kScrSlots = 24576;                   // kMaxSlots x 3 x int64 from the phase kernels
 constexpr int kMaxSlots = 1024;
-constexpr size_t kScrBytes = kScrSlots + (size_t)kMaxSlots * 24;  // 40960
+constexpr size_t kScrBytes = kScrSlots + (size_t)kMaxSlots * 24;  // 49152
 
 // Per-lattice descriptor kept in the lattice's scratch, read by the batched
 // kernel.  next_sweep is advanced on the device by every path that sweeps.
@@ -100,9 +103,10 @@ bool persistent_2bit_supported(int L, const Tuning2Bit &t, int *grid, int *rows)
 hipError_t launch_sweeps_2bit(const PhaseArgs &a, const Tuning2Bit &t, uint32_t sweeps, unsigned *counter,
                               unsigned *err, hipStream_t s);
 hipError_t launch_zero_i64(unsigned long long *p, int n, hipStream_t s);
-// Tracker total = base triple + all slots, written at scratch + kScrTrack.
-hipError_t launch_sum_tracker(uint8_t *scratch, hipStream_t s);
-hipError_t launch_observables(const void *state, int L, int encoding, unsigned long long *obs, hipStream_t s);
+// Observable sums of the whole lattice into the observable slots (one block
+// per slot, at most kMaxObsSlots blocks), then the fold of slots into the
+// totals at scratch + kScrTrack (tracker) and + kScrObs (observables).
+hipError_t launch_observables(uint8_t *scratch, const void *state, int L, int encoding, hipStream_t s);
 // Batched kernel; dynamic LDS is sized for the largest L.  threads = block
 // size (a multiple of 64, at most 1024; 0 = min(1024, N/16 of the largest L)).
 hipError_t launch_sweep_lds(const BatchArgs &a, int max_L, int threads, hipStream_t s);

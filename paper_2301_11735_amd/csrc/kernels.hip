@@ -454,16 +454,36 @@ __global__ void k_zero_i64(unsigned long long *p, int n)
 __device__ __forceinline__ int spin_of(uint32_t c) { return (c & 2u) ? 0 : 1 - 2 * (int)(c & 1u); }
 __device__ __forceinline__ int charge_of(uint32_t c) { return (c & 2u) ? 1 - 2 * (int)(c & 1u) : 0; }
 
-__global__ void __launch_bounds__(256) k_obs_int8(const int8_t *__restrict__ st, int L,
-                                                  unsigned long long *obs)
+// Block-level sum of K values written (not added) to dst[0..K): no atomics.
+template <int K, typename T>
+__device__ __forceinline__ void block_reduce_store(T (&v)[K], long long *dst)
+{
+    __shared__ long long part[16][K];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < K; ++i) part[wave][i] = (long long)v[i];
+    __syncthreads();
+    if (threadIdx.x < K) {
+        const int nw = (blockDim.x + 63) >> 6;
+        long long s = 0;
+        for (int w = 0; w < nw; ++w) s += part[w][threadIdx.x];
+        dst[threadIdx.x] = s;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_obs_int8(const int8_t *__restrict__ st, int L, long long *slots)
 {
     long long v[7] = {0, 0, 0, 0, 0, 0, 0};
-    const size_t N = (size_t)L * L;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
-        const int y = (int)(i / L), x = (int)(i - (size_t)y * L);
+    const uint32_t N = (uint32_t)L * (uint32_t)L;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        const int y = (int)(i / (uint32_t)L), x = (int)(i - (uint32_t)y * L);
         const uint32_t c = (uint32_t)st[i];
-        const uint32_t cr = (uint32_t)st[(size_t)y * L + (x + 1 == L ? 0 : x + 1)];
-        const uint32_t cd = (uint32_t)st[(size_t)(y + 1 == L ? 0 : y + 1) * L + x];
+        const uint32_t cr = (uint32_t)st[(uint32_t)y * L + (x + 1 == L ? 0 : x + 1)];
+        const uint32_t cd = (uint32_t)st[(uint32_t)(y + 1 == L ? 0 : y + 1) * L + x];
         const int S = charge_of(c), G = spin_of(c), sg = ((x + y) & 1) ? -1 : 1;
         v[0] += S;
         v[1] += S * S;
@@ -473,7 +493,7 @@ __global__ void __launch_bounds__(256) k_obs_int8(const int8_t *__restrict__ st,
         v[5] += sg * G;
         v[6] += sg * S;
     }
-    block_reduce_add<7>(v, obs);
+    block_reduce_store<7>(v, slots + 7 * (size_t)blockIdx.x);
 }
 
 // Bond sums of 16 sites (h, l bit planes) with 16 partner sites (hp, lp):
@@ -486,24 +506,21 @@ __device__ __forceinline__ void bond_sums(uint32_t h, uint32_t l, uint32_t hp, u
     bss += __popc(mm & ~diff) - __popc(mm & diff);
 }
 
-__global__ void __launch_bounds__(256) k_obs_2bit(const uint32_t *__restrict__ st, int L,
-                                                  unsigned long long *obs)
+// One class word (16 sites) per thread: its right neighbours are the same
+// word of the next class (or class 0 one site on), its lower neighbours the
+// same word of the paired row class.  Popcounts over the bit planes.
+__global__ void __launch_bounds__(1024) k_obs_2bit(const uint32_t *__restrict__ st, int L, long long *slots)
 {
     long long v[7] = {0, 0, 0, 0, 0, 0, 0};
-    const int W = L >> 6, H = L >> 1, Lq = L >> 2;
-    const size_t csz = (size_t)H * W, nwords = 8 * csz;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nwords;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i / csz);
-        const size_t rem = i - (size_t)c * csz;
-        const int Y = (int)(rem / W), j = (int)(rem - (size_t)Y * W);
-        const int cx = c & 3, cy = c >> 2;
+    const uint32_t W = (uint32_t)L >> 6, H = (uint32_t)L >> 1, Lq = (uint32_t)L >> 2;
+    const uint32_t csz = H * W, nwords = 8u * csz;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x) {
+        const uint32_t c = i / csz, rem = i - c * csz;
+        const uint32_t Y = rem / W, j = rem - Y * W;
+        const uint32_t cx = c & 3u, cy = c >> 2;
         const uint32_t w = st[i];
-        const uint32_t wr = cx < 3 ? st[i + csz]
-                                   : load16(st, (uint32_t)((size_t)(4 * cy) * csz + (size_t)Y * W), W,
-                                            16 * j + 1 == Lq ? 0 : 16 * j + 1);
-        const uint32_t wd = cy == 0 ? st[i + 4 * csz]
-                                    : st[(size_t)cx * csz + (size_t)(Y + 1 == H ? 0 : Y + 1) * W + j];
+        const uint32_t wr = cx < 3 ? st[i + csz] : load16(st, 4u * cy * csz + Y * W, (int)W, 16 * j + 1 == Lq ? 0 : (int)(16 * j + 1));
+        const uint32_t wd = cy == 0 ? st[i + 4 * csz] : st[cx * csz + (Y + 1 == H ? 0 : Y + 1) * W + j];
         const uint32_t h = (w >> 1) & kM5, l = w & kM5;
         const int sumS = __popc(h & ~l) - __popc(h & l);
         const int sumG = __popc((h | l) ^ kM5) - __popc(l & ~h);
@@ -519,7 +536,7 @@ __global__ void __launch_bounds__(256) k_obs_2bit(const uint32_t *__restrict__ s
         v[5] += sg * sumG;
         v[6] += sg * sumS;
     }
-    block_reduce_add<7>(v, obs);
+    block_reduce_store<7>(v, slots + 7 * (size_t)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -727,26 +744,28 @@ __global__ void __launch_bounds__(256) k_obs_batch(BatchArgs args, unsigned long
     block_reduce_add<3>(t3, o);
 }
 
-// Tracker total of one lattice: base triple plus every per-block slot.
-__global__ void __launch_bounds__(256) k_sum_tracker(uint8_t *scr)
+// Totals of one lattice: tracker = base triple + every tracker slot;
+// observables = the first n_obs observable slots.
+__global__ void __launch_bounds__(256) k_fold_sums(uint8_t *scr, int n_obs)
 {
-    long long t3[3] = {0, 0, 0};
+    long long t[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const long long *slots = (const long long *)(scr + kScrSlots);
     for (int i = threadIdx.x; i < kMaxSlots; i += blockDim.x) {
-        t3[0] += slots[3 * i];
-        t3[1] += slots[3 * i + 1];
-        t3[2] += slots[3 * i + 2];
+        t[0] += slots[3 * i];
+        t[1] += slots[3 * i + 1];
+        t[2] += slots[3 * i + 2];
     }
     if (threadIdx.x == 0) {
         const long long *base = (const long long *)(scr + kScrTrackBase);
-        t3[0] += base[0];
-        t3[1] += base[1];
-        t3[2] += base[2];
+        t[0] += base[0];
+        t[1] += base[1];
+        t[2] += base[2];
     }
-    unsigned long long *out = (unsigned long long *)(scr + kScrTrack);
-    if (threadIdx.x < 3) out[threadIdx.x] = 0ull;
-    __syncthreads();
-    block_reduce_add<3>(t3, out);
+    const long long *os = (const long long *)(scr + kScrObsSlots);
+    for (int i = threadIdx.x; i < n_obs; i += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 7; ++k) t[3 + k] += os[7 * i + k];
+    block_reduce_store<10>(t, (long long *)(scr + kScrTrack));
 }
 
 int g_num_cus = 0;
@@ -840,11 +859,6 @@ hipError_t launch_sweeps_2bit(const PhaseArgs &a, const Tuning2Bit &t, uint32_t 
     return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), kargs, (size_t)block * 8u, s);
 }
 
-hipError_t launch_sum_tracker(uint8_t *scratch, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_sum_tracker, dim3(1), dim3(256), 0, s, scratch);
-    return hipGetLastError();
-}
 
 hipError_t launch_zero_i64(unsigned long long *p, int n, hipStream_t s)
 {
@@ -852,18 +866,19 @@ hipError_t launch_zero_i64(unsigned long long *p, int n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_observables(const void *state, int L, int encoding, unsigned long long *obs, hipStream_t s)
+hipError_t launch_observables(uint8_t *scratch, const void *state, int L, int encoding, hipStream_t s)
 {
-    hipError_t e = launch_zero_i64(obs, 7, s);
-    if (e != hipSuccess) return e;
-    const size_t units = encoding == 0 ? (size_t)L * L : (size_t)L * L / 16;
-    size_t grid = (units + 255) / 256;
-    const size_t cap = 8u * (size_t)num_cus();
-    if (grid > cap) grid = cap;
+    const uint32_t units = encoding == 0 ? (uint32_t)L * L : (uint32_t)L * L / 16u;
+    uint32_t grid = (units + 1023u) / 1024u;
+    if (grid > (uint32_t)kMaxObsSlots) grid = (uint32_t)kMaxObsSlots;
+    long long *slots = (long long *)(scratch + kScrObsSlots);
     if (encoding == 0)
-        hipLaunchKernelGGL(k_obs_int8, dim3((unsigned)grid), dim3(256), 0, s, (const int8_t *)state, L, obs);
+        hipLaunchKernelGGL(k_obs_int8, dim3(grid), dim3(1024), 0, s, (const int8_t *)state, L, slots);
     else
-        hipLaunchKernelGGL(k_obs_2bit, dim3((unsigned)grid), dim3(256), 0, s, (const uint32_t *)state, L, obs);
+        hipLaunchKernelGGL(k_obs_2bit, dim3(grid), dim3(1024), 0, s, (const uint32_t *)state, L, slots);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fold_sums, dim3(1), dim3(256), 0, s, scratch, (int)grid);
     return hipGetLastError();
 }
 

@@ -663,9 +663,7 @@ int lattice_observables(lattice *h, lat_obs *out)
     if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
     if (!out) return fail(LAT_EINVAL, "null output");
     unsigned long long *track = (unsigned long long *)(h->d_scratch + kScrTrack);
-    unsigned long long *obs = (unsigned long long *)(h->d_scratch + kScrObs);
-    hipError_t e = launch_observables(h->d_state, h->L, h->enc, obs, h->stream);
-    if (e == hipSuccess) e = launch_sum_tracker(h->d_scratch, h->stream);
+    hipError_t e = launch_observables(h->d_scratch, h->d_state, h->L, h->enc, h->stream);
     int64_t v[11];  // tracker, 7 sums, error flags
     if (e == hipSuccess) e = hipMemcpyAsync(v, track, sizeof(v), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
