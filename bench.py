@@ -147,33 +147,88 @@ def cpu_baseline(spec: workloads.LatticeSpec, sweeps: int) -> dict:
     }
 
 
-def batched_run(torch, lat) -> dict:
+def batched_run(torch, lat, b2b_sample: int = 8, b2b_sweeps: int = 1000) -> dict:
     """The batched workload: 256 L=128 lattices (32 temperatures x 8
-    densities), 5000 sweeps each, observables every 50 sweeps, in batched
-    launches.  Lattice creation is not timed."""
+    densities), 5000 sweeps each, observables every 50 sweeps.  Timed two
+    ways on fresh lattices: the whole job as one replay of a HIP graph holding
+    its 100 intervals (batched sweep launch + batched observable reduction
+    into that interval's slot, the series read back once at the end), and
+    eagerly, one batched sweep call and one observables read per interval.
+    Lattice creation, graph capture and the launch-shape autotuning (the first
+    calls for a new batch shape) are not timed.  Beside them, a sample of the
+    same lattices run back to back through the single-lattice call."""
     specs = workloads.batched_specs()
-    lats = [lat.Lattice(s.L, s.n, s.Delta, s.V, s.J, s.T, s.seed, encoding=s.encoding) for s in specs]
-    obs = lat.BatchObservables(len(lats))
     every, total = specs[0].every, specs[0].sweeps
-    lat.sweep_batch(lats, every)  # warm-up interval (not counted)
-    obs(lats)
+    intervals = total // every
+    updates = sum(s.L * s.L for s in specs) * total
+
+    def fresh():
+        return [lat.Lattice(s.L, s.n, s.Delta, s.V, s.J, s.T, s.seed, encoding=s.encoding) for s in specs]
+
+    # autotune the batch shape on throw-away lattices
+    warm = fresh()
+    wobs = lat.BatchObservables(len(warm))
+    for _ in range(6):
+        lat.sweep_batch(warm, every)
+        wobs(warm)
+    for g in warm:
+        g.destroy()
+
+    lats = fresh()
+    graph = lat.BatchGraph(lats, every, intervals)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(total // every):
+    graph.launch(1)
+    series = graph.read()  # synchronises
+    dt_graph = time.perf_counter() - t0
+    graph.destroy()
+    last_graph = series[-1]
+    for g in lats:
+        g.destroy()
+
+    lats = fresh()
+    obs = lat.BatchObservables(len(lats))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(intervals):
         lat.sweep_batch(lats, every)
         last = obs(lats)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    for s, o in zip(specs, last):
+    for s, o, og in zip(specs, last, last_graph):
         Q, _ = lat.charge_target(s.L, s.n)
         assert o.sum_S == Q
-    updates = sum(s.L * s.L for s in specs) * total
-    return {
+        assert o.as_dict() == og.as_dict(), "graph and eager runs differ"
+    for g in lats:
+        g.destroy()
+    out = {
         "workload": "256 lattices L=128 2-bit, T in [0.2,2.0] x n in {0..0.35}, 5000 sweeps, observables every 50",
-        "lattices_per_s": len(specs) / dt,
-        "site_updates_per_s": updates / dt,
-        "seconds": dt,
+        "lattices_per_s": len(specs) / dt_graph,
+        "site_updates_per_s": updates / dt_graph,
+        "seconds": dt_graph,
+        "form": "one HIP graph replay holding all 100 intervals (sweeps + observables), series read once",
+        "eager": {"lattices_per_s": len(specs) / dt, "site_updates_per_s": updates / dt, "seconds": dt},
     }
+    if b2b_sample > 0:
+        sample = specs[:: len(specs) // b2b_sample][:b2b_sample]
+        busy = 0.0
+        for s in sample:
+            g = lat.Lattice(s.L, s.n, s.Delta, s.V, s.J, s.T, s.seed, encoding=s.encoding)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(b2b_sweeps // every):
+                g.sweep(every)
+                g.observables()
+            torch.cuda.synchronize()
+            busy += time.perf_counter() - t1
+            g.destroy()
+        b2b = sum(s.L * s.L for s in sample) * (b2b_sweeps // every * every) / busy
+        out["back_to_back"] = {
+            "sample": f"{len(sample)} of the lattices, {b2b_sweeps} sweeps each, one lattice_sweep at a time",
+            "site_updates_per_s": b2b,
+        }
+        out["batched_over_back_to_back"] = out["site_updates_per_s"] / b2b
+    return out
 
 
 def served_run(seconds: float) -> dict:

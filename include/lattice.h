@@ -142,6 +142,33 @@ int lattice_sweep_batch(lattice *const *hs, int32_t count, uint32_t sweeps, void
 int lattice_observables_batch(lattice *const *hs, int32_t count, void *d_out, size_t out_bytes, lat_obs *out,
                               void *hip_stream);
 
+/* Batched observation intervals captured once into a HIP graph (section 3.2,
+ * lattice copies advanced together).  One replay runs `intervals` intervals;
+ * each advances the `count` lattices by `sweeps` sweeps and reduces their
+ * observables into its own slot of the device buffer d_out (slot k at byte
+ * 80*count*k, 80 bytes per lattice, as lattice_observables_batch), so a whole
+ * observable series is produced with one graph launch and read with one copy.
+ * Every lattice must take the on-chip batched path (L <= 512).  The capture
+ * runs on a private stream and launches nothing; replays run on hip_stream,
+ * which the caller orders after the lattices' other work.  The lattices and
+ * d_out must outlive the graph.
+ * Errors: LAT_EINVAL (empty or duplicate batch, sweeps == 0, intervals == 0,
+ * a lattice with L > 512, null pointers), LAT_ENOMEM (d_out smaller than
+ * 80*count*intervals bytes), LAT_ESTATE, LAT_EHIP. */
+typedef struct lat_batch_graph lat_batch_graph;
+int lattice_batch_graph_create(lattice *const *hs, int32_t count, uint32_t sweeps, uint32_t intervals, void *d_out,
+                               size_t out_bytes, void *hip_stream, lat_batch_graph **out);
+/* Enqueue `times` replays on the graph's stream (asynchronous).  Errors:
+ * LAT_ESTATE, LAT_EHIP. */
+int lattice_batch_graph_launch(lat_batch_graph *g, uint32_t times);
+/* Synchronise the graph's stream and convert d_out, as written by the last
+ * replay, into intervals*count records (interval-major: record k*count + i is
+ * lattice i after interval k).  Errors: LAT_ESTATE, LAT_EINVAL, LAT_EHIP. */
+int lattice_batch_graph_read(lat_batch_graph *g, lat_obs *out);
+/* Synchronise the graph's stream and release the graph (caller memory
+ * untouched).  Errors: LAT_ESTATE, LAT_EHIP. */
+int lattice_batch_graph_destroy(lat_batch_graph *g);
+
 /* ---------------------------------------------------------------------------
  * Serving: simulation requests that arrive while others run.  The server
  * admits queued requests, in arrival order, into the caller's device pool when

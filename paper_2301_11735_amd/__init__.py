@@ -28,6 +28,10 @@ EXPORTS = (
     "lattice_read_state",
     "lattice_sweep_batch",
     "lattice_observables_batch",
+    "lattice_batch_graph_create",
+    "lattice_batch_graph_launch",
+    "lattice_batch_graph_read",
+    "lattice_batch_graph_destroy",
     "lattice_destroy",
     "lattice_last_error",
     "lat_server_create",
@@ -140,6 +144,15 @@ def lib() -> ctypes.CDLL:
         L.lattice_sweep_batch.restype = ctypes.c_int
         L.lattice_observables_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, vp, sz, ctypes.POINTER(LatObs), vp]
         L.lattice_observables_batch.restype = ctypes.c_int
+        L.lattice_batch_graph_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint32,
+                                                 vp, sz, vp, ctypes.POINTER(vp)]
+        L.lattice_batch_graph_create.restype = ctypes.c_int
+        L.lattice_batch_graph_launch.argtypes = [vp, ctypes.c_uint32]
+        L.lattice_batch_graph_launch.restype = ctypes.c_int
+        L.lattice_batch_graph_read.argtypes = [vp, ctypes.POINTER(LatObs)]
+        L.lattice_batch_graph_read.restype = ctypes.c_int
+        L.lattice_batch_graph_destroy.argtypes = [vp]
+        L.lattice_batch_graph_destroy.restype = ctypes.c_int
         L.lattice_destroy.argtypes = [vp]
         L.lattice_destroy.restype = ctypes.c_int
         L.lat_server_create.argtypes = [vp, sz, ctypes.c_int32, ctypes.c_uint64, vp, ctypes.POINTER(vp)]
@@ -281,6 +294,40 @@ class BatchObservables:
         _check(lib().lattice_observables_batch(_handles(lattices), n, self.buf.data_ptr(), self.buf.numel(), out,
                                                _stream_handle(stream)))
         return list(out)[:n]
+
+
+class BatchGraph:
+    """`intervals` observation intervals of a batch (each: `sweeps` sweeps of
+    every lattice, then their observables) captured into one HIP graph;
+    launch() replays it, read() returns the observables of the last replay as
+    a list of `intervals` lists (one record per lattice)."""
+
+    def __init__(self, lattices, sweeps: int, intervals: int = 1, stream=None, device: str = "cuda"):
+        import torch
+
+        self._lats = list(lattices)  # keep the lattices (and their buffers) alive
+        self.intervals = intervals
+        self.buf = torch.empty(80 * max(1, len(self._lats)) * intervals, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        _check(lib().lattice_batch_graph_create(_handles(self._lats), len(self._lats), sweeps, intervals,
+                                                self.buf.data_ptr(), self.buf.numel(), _stream_handle(stream),
+                                                ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, times: int = 1):
+        _check(lib().lattice_batch_graph_launch(self._h, times))
+
+    def read(self) -> list:
+        n = len(self._lats)
+        out = (LatObs * (n * self.intervals))()
+        _check(lib().lattice_batch_graph_read(self._h, out))
+        flat = list(out)
+        return [flat[k * n:(k + 1) * n] for k in range(self.intervals)]
+
+    def destroy(self):
+        if self._h:
+            _check(lib().lattice_batch_graph_destroy(self._h))
+            self._h = None
 
 
 class Server:

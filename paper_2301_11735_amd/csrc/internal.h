@@ -30,8 +30,12 @@ int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
 bool live(const lattice *h);
 // Advance lattices resident in LDS; lattice i by sweeps[i] (null: `uniform`).
+// tune = false: no autotuning launches (the tuned or default block size),
+// as needed under stream capture.
 int enqueue_lds_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps, uint32_t uniform,
-                       hipStream_t stream);
+                       hipStream_t stream, bool tune = true);
+// One batched observables launch per 256 lattices into dev (10 int64 each).
+int enqueue_observables_batch(lattice *const *hs, int32_t count, unsigned long long *dev, hipStream_t stream);
 int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream);
 // v = (tracker nD, nV, nJ, sum S, sum S^2, bonds SS, bonds ss, M, M_st, C_st).
 void fill_obs(const lattice *h, const int64_t *v, lat_obs *out);
@@ -41,7 +45,8 @@ void fill_obs(const lattice *h, const int64_t *v, lat_obs *out);
 // HIP events on the call's stream, then keeps the fastest per site update.
 // The chain does not depend on the launch shape, so tuning runs real work.
 // LATTICE_BATCH_THREADS=<n> pins the block size instead.
-int batch_threads_for(int max_L, int count, hipStream_t stream, hipEvent_t *start, hipEvent_t *stop, int *slot);
+int batch_threads_for(int max_L, int count, bool word, hipStream_t stream, hipEvent_t *start, hipEvent_t *stop,
+                      int *slot);
 void batch_threads_done(int slot, double site_updates);
 
 }  // namespace detail

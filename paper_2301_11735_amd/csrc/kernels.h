@@ -109,7 +109,11 @@ hipError_t launch_zero_i64(unsigned long long *p, int n, hipStream_t s);
 hipError_t launch_observables(uint8_t *scratch, const void *state, int L, int encoding, hipStream_t s);
 // Batched kernel; dynamic LDS is sized for the largest L.  threads = block
 // size (a multiple of 64, at most 1024; 0 = min(1024, N/16 of the largest L)).
-hipError_t launch_sweep_lds(const BatchArgs &a, int max_L, int threads, hipStream_t s);
+// One-time kernel set-up (dynamic LDS limits); called before the first launch.
+hipError_t init_kernel_attributes();
+// Batched sweeps with each lattice resident in LDS.  word = every lattice of
+// the batch has L % 64 == 0 (word-parallel form); otherwise the per-site form.
+hipError_t launch_sweep_lds(const BatchArgs &a, int max_L, int threads, bool word, hipStream_t s);
 // desc->next_sweep += sweeps (after host-scheduled phase launches).
 hipError_t launch_advance(LatDesc *desc, uint32_t sweeps, hipStream_t s);
 // Observables of `count` lattices in one launch: out[10*b .. 10*b+9] =

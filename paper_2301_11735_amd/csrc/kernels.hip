@@ -564,24 +564,12 @@ __device__ __forceinline__ uint32_t lds_code(const uint32_t *lat, const LdsGeom 
     return (lat[g.word(c, Y, X)] >> (2 * (X & 15))) & 3u;
 }
 
-__global__ void __launch_bounds__(1024) k_sweep_lds(BatchArgs args)
+// Copy a lattice from its global state into the LDS class arrays (rows of
+// Wp words, 16 sites per word; int8 states are packed on the way in), and back.
+__device__ __forceinline__ void stage_lattice(uint32_t *lat, const LatDesc &d, const LdsGeom &g)
 {
-    __shared__ uint2 s_tab[kDevTabEntries];
-    __shared__ uint2 s_trans[kTransEntries];
-    extern __shared__ uint32_t lat[];
-    uint8_t *scr = args.scratch[blockIdx.x];
-    const LatDesc d = *(const LatDesc *)(scr + kScrDesc);
-    stage_tables(s_tab, s_trans, (const uint2 *)(scr + kScrDevTab), (const uint2 *)(scr + kScrTrans));
-    LdsGeom g;
-    g.L = d.L;
-    g.Lq = d.L >> 2;
-    g.H = d.L >> 1;
-    g.Wp = (g.Lq + 15) >> 4;
-    g.csz = (uint32_t)g.H * g.Wp;
-    const int L = g.L, Lq = g.Lq, H = g.H;
+    const int L = g.L, Lq = g.Lq;
     const uint32_t nwords = 8u * g.csz;
-
-    // global -> LDS
     if (d.enc == 1) {
         const uint32_t *src = (const uint32_t *)d.state;  // same layout, Wp = L/64
         for (uint32_t i = threadIdx.x; i < nwords; i += blockDim.x) lat[i] = src[i];
@@ -600,6 +588,41 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(BatchArgs args)
             lat[i] = v;
         }
     }
+}
+
+__device__ __forceinline__ void unstage_lattice(const uint32_t *lat, const LatDesc &d, const LdsGeom &g)
+{
+    const int L = g.L;
+    if (d.enc == 1) {
+        uint32_t *dst = (uint32_t *)d.state;
+        for (uint32_t i = threadIdx.x; i < 8u * g.csz; i += blockDim.x) dst[i] = lat[i];
+    } else {
+        int8_t *dst = (int8_t *)d.state;
+        for (uint32_t i = threadIdx.x; i < (uint32_t)L * L; i += blockDim.x) {
+            const int y = (int)(i / L), x = (int)(i - (uint32_t)y * L);
+            dst[i] = (int8_t)lds_code(lat, g, 4 * (y & 1) + (x & 3), y >> 1, x >> 2);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_sweep_lds(BatchArgs args)
+{
+    __shared__ uint2 s_tab[kDevTabEntries];
+    __shared__ uint2 s_trans[kTransEntries];
+    extern __shared__ uint32_t lat[];
+    uint8_t *scr = args.scratch[blockIdx.x];
+    const LatDesc d = *(const LatDesc *)(scr + kScrDesc);
+    stage_tables(s_tab, s_trans, (const uint2 *)(scr + kScrDevTab), (const uint2 *)(scr + kScrTrans));
+    LdsGeom g;
+    g.L = d.L;
+    g.Lq = d.L >> 2;
+    g.H = d.L >> 1;
+    g.Wp = (g.Lq + 15) >> 4;
+    g.csz = (uint32_t)g.H * g.Wp;
+    const int L = g.L, Lq = g.Lq, H = g.H;
+    const uint32_t nwords = 8u * g.csz;
+
+    stage_lattice(lat, d, g);
     __syncthreads();
 
     const uint32_t n_calls = (uint32_t)L * (uint32_t)L / 16u;
@@ -650,17 +673,223 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(BatchArgs args)
         }
     }
 
-    // LDS -> global
-    if (d.enc == 1) {
-        uint32_t *dst = (uint32_t *)d.state;
-        for (uint32_t i = threadIdx.x; i < nwords; i += blockDim.x) dst[i] = lat[i];
+    unstage_lattice(lat, d, g);
+    if (threadIdx.x == 0) ((LatDesc *)(scr + kScrDesc))->next_sweep = d.next_sweep + my_sweeps;
+    block_reduce_add<3>(tr, (unsigned long long *)(scr + kScrTrackBase));
+}
+
+// ---------------------------------------------------------------------------
+// Batched sweeps, word-parallel form, for lattices with L % 64 == 0: the LDS
+// copy has the global 2-bit class layout (W = L/64 words per class row), and
+// a phase is computed 16 sites at a time as in the single-lattice phase
+// kernel.  The 16 pairs of an a-word are split among Q threads (Q = 1, 2, 4
+// or 8, chosen per lattice so that the block is filled): thread q of a word
+// takes the Philox calls c with c % Q == q, i.e. sites 2c and 2c+1.
+//
+// Within a phase no updated site neighbours another updated site, so every
+// neighbour word read is constant during the phase; the a-word and the two
+// b-words a thread updates are shared with other threads only in bit fields
+// that those threads neither read nor write, and the updates are applied as
+// LDS xor atomics of the changed bits (a plain store when Q = 1 for the a-word).
+
+// (r0.byte k, r1.byte k, r2.byte k, r3.byte k) with sel = k | (4 + k) << 8 | 0x0C0C0000.
+__device__ __forceinline__ uint32_t gather_byte(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t r3, uint32_t sel)
+{
+    const uint32_t lo = __builtin_amdgcn_perm(r1, r0, sel);
+    const uint32_t hi = __builtin_amdgcn_perm(r3, r2, sel);
+    return __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+}
+
+struct WordPhase {
+    uint32_t oA0, oAL, oAR, oAV, oB0, oBL, oBR, oBV;  // class offsets (words)
+    int W, H, Lq, dX, k, p, pb;
+    uint32_t magicW;                                 // ceil(2^32 / W)
+    uint32_t s_lo, s_hi, key0, key1;
+};
+
+// Barrier = true keeps the compiler from interleaving the Philox calls of a
+// task (fewer live registers, needed at 1024 threads per block); without it
+// the calls overlap each other's LDS table lookups.
+template <int Q, bool Barrier>
+__device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uint32_t task, const uint2 *s_tab,
+                                          const uint2 *s_trans, int (&tr)[3])
+{
+    constexpr int LOGQ = Q == 1 ? 0 : Q == 2 ? 1 : Q == 4 ? 2 : 3;
+    const uint32_t wi = task >> LOGQ;
+    const int q = (int)(task & (uint32_t)(Q - 1));
+    const int W = f.W, H = f.H, Lq = f.Lq;
+    const int Y = W == 1 ? (int)wi : (int)__umulhi(wi, f.magicW), j = (int)wi - Y * W;
+    int Xb = 16 * j + f.dX;
+    if (Xb >= Lq) Xb -= Lq;
+    const int Yb = Y + f.k >= H ? Y + f.k - H : Y + f.k;
+    const int xAL = f.p > 0 ? 16 * j : (j == 0 ? Lq - 1 : 16 * j - 1);
+    const int xAR = f.p < 3 ? 16 * j : 16 * j + 1;
+    const int xBL = f.pb > 0 ? Xb : (Xb == 0 ? Lq - 1 : Xb - 1);
+    const int xBR = f.pb < 3 ? Xb : (Xb + 1 == Lq ? 0 : Xb + 1);
+    const uint32_t ro = (uint32_t)Y * W, rob = (uint32_t)Yb * W;
+    const uint32_t roU = (uint32_t)(Y == 0 ? H - 1 : Y - 1) * W;
+    const uint32_t robD = (uint32_t)(Yb + 1 == H ? 0 : Yb + 1) * W;
+
+    const uint32_t A0 = lat[f.oA0 + ro + j];
+    const uint32_t B0 = load16(lat, f.oB0 + rob, W, Xb);
+    const SideSums sa = side_sums(load16(lat, f.oAL + ro, W, xAL), load16(lat, f.oAR + ro, W, xAR),
+                                  lat[f.oAV + roU + j], lat[f.oAV + ro + j]);
+    const SideSums sb = side_sums(load16(lat, f.oBL + rob, W, xBL), load16(lat, f.oBR + rob, W, xBR),
+                                  load16(lat, f.oBV + rob, W, Xb), load16(lat, f.oBV + robD, W, Xb));
+
+    const uint32_t call0 = (uint32_t)Y * (uint32_t)(Lq >> 1) + 8u * (uint32_t)j;
+    uint32_t dA = 0u, dB = 0u, packed = 0u;
+    auto do_call = [&](int c, uint32_t be, uint32_t bo) {
+        const u32x4 w = philox4x32_10(f.s_lo, (uint32_t)f.p, call0 + (uint32_t)c, f.s_hi, f.key0, f.key1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int t = 2 * c + h;
+            const uint32_t s0 = ((A0 >> (2 * t)) & 3u) | (((B0 >> (2 * t)) & 3u) << 2);
+            const uint32_t ns = pair_step(s0, h ? bo : be, h ? w.z : w.x, h ? w.w : w.y, s_trans, s_tab, packed);
+            const uint32_t dd = ns ^ s0;
+            dA |= (dd & 3u) << (2 * t);
+            dB |= (dd >> 2) << (2 * t);
+        }
+    };
+    if constexpr (Q <= 2) {
+#pragma unroll
+        for (int hh = 0; hh < (Q == 1 ? 2 : 1); ++hh) {
+            const int half = Q == 1 ? hh : q;
+            const int sh = 4 * half;
+            uint32_t ge[4], go[4];
+            transpose4((sa.ES >> sh) & kM0F, (sb.ES >> sh) & kM0F, (sa.EG >> sh) & kM0F, (sb.EG >> sh) & kM0F,
+                       ge[0], ge[1], ge[2], ge[3]);
+            transpose4((sa.OS >> sh) & kM0F, (sb.OS >> sh) & kM0F, (sa.OG >> sh) & kM0F, (sb.OG >> sh) & kM0F,
+                       go[0], go[1], go[2], go[3]);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                do_call(2 * kk + half, ge[kk], go[kk]);
+                if (Barrier) __builtin_amdgcn_sched_barrier(0);
+            }
+        }
     } else {
-        int8_t *dst = (int8_t *)d.state;
-        for (uint32_t i = threadIdx.x; i < (uint32_t)L * L; i += blockDim.x) {
-            const int y = (int)(i / L), x = (int)(i - (uint32_t)y * L);
-            dst[i] = (int8_t)lds_code(lat, g, 4 * (y & 1) + (x & 3), y >> 1, x >> 2);
+        const int half = q & 1, sh = 4 * half;
+        const uint32_t rES0 = (sa.ES >> sh) & kM0F, rES1 = (sb.ES >> sh) & kM0F;
+        const uint32_t rEG0 = (sa.EG >> sh) & kM0F, rEG1 = (sb.EG >> sh) & kM0F;
+        const uint32_t rOS0 = (sa.OS >> sh) & kM0F, rOS1 = (sb.OS >> sh) & kM0F;
+        const uint32_t rOG0 = (sa.OG >> sh) & kM0F, rOG1 = (sb.OG >> sh) & kM0F;
+#pragma unroll
+        for (int i = 0; i < 8 / Q; ++i) {
+            const uint32_t kk = (uint32_t)(q >> 1) + 2u * (uint32_t)i;
+            const uint32_t sel = kk | ((4u + kk) << 8) | 0x0C0C0000u;
+            do_call(2 * (int)kk + half, gather_byte(rES0, rES1, rEG0, rEG1, sel),
+                    gather_byte(rOS0, rOS1, rOG0, rOG1, sel));
         }
     }
+    unpack_tracker(packed, tr);
+    if (Q == 1) {
+        if (dA) lat[f.oA0 + ro + j] = A0 ^ dA;
+    } else if (dA) {
+        atomicXor(&lat[f.oA0 + ro + j], dA);
+    }
+    if (dB) {
+        const int jb = Xb >> 4, shb = Xb & 15;
+        atomicXor(&lat[f.oB0 + rob + (uint32_t)jb], dB << (2 * shb));
+        if (shb) {
+            const uint32_t hi = dB >> (32 - 2 * shb);
+            if (hi) atomicXor(&lat[f.oB0 + rob + (uint32_t)(jb + 1 == W ? 0 : jb + 1)], hi);
+        }
+    }
+}
+
+template <int Q, bool Barrier>
+__device__ __forceinline__ void word_sweeps(uint32_t *lat, uint32_t *sched, const LatDesc &d, uint32_t my_sweeps,
+                                            const uint2 *s_tab, const uint2 *s_trans, int (&tr)[3])
+{
+    WordPhase f;
+    f.W = d.L >> 6;
+    f.H = d.L >> 1;
+    f.Lq = d.L >> 2;
+    f.magicW = f.W == 1 ? 0u : (uint32_t)((0x100000000ull + (uint64_t)f.W - 1u) / (uint64_t)f.W);
+    f.key0 = d.key0;
+    f.key1 = d.key1;
+    const uint32_t csz = (uint32_t)f.H * (uint32_t)f.W;
+    const uint32_t tasks = csz * (uint32_t)Q;
+    for (uint32_t i = 0; i < my_sweeps; ++i) {
+        const uint64_t s = d.next_sweep + i;
+        const uint32_t *Wd = sched + 12u * (i & 1u);
+        const int r = __builtin_amdgcn_readfirstlane(1 + (int)(((Wd[0] >> 8) * 3u) >> 24));
+        f.s_lo = (uint32_t)s;
+        f.s_hi = (uint32_t)(s >> 32);
+        for (int p = 0; p < 4; ++p) {
+            const int m = __builtin_amdgcn_readfirstlane((int)mulhi_u32(Wd[1 + 2 * p], (uint32_t)f.Lq));
+            f.k = __builtin_amdgcn_readfirstlane((int)mulhi_u32(Wd[2 + 2 * p], (uint32_t)f.H));
+            f.p = p;
+            f.pb = (p + r) & 3;
+            const int carry = (p + r) >> 2;
+            f.dX = m + carry >= f.Lq ? m + carry - f.Lq : m + carry;
+            f.oA0 = (uint32_t)p * csz;
+            f.oAL = (uint32_t)(p > 0 ? p - 1 : 3) * csz;
+            f.oAR = (uint32_t)(p < 3 ? p + 1 : 0) * csz;
+            f.oAV = (uint32_t)(4 + p) * csz;
+            f.oB0 = (uint32_t)(4 + f.pb) * csz;
+            f.oBL = (uint32_t)(f.pb > 0 ? 4 + f.pb - 1 : 7) * csz;
+            f.oBR = (uint32_t)(f.pb < 3 ? 4 + f.pb + 1 : 4) * csz;
+            f.oBV = (uint32_t)f.pb * csz;
+            // the next sweep's schedule words, into the other buffer (read
+            // after this phase's barrier)
+            if (p == 3 && threadIdx.x < 3 && i + 1 < my_sweeps) {
+                const u32x4 w = philox4x32_10((uint32_t)(s + 1), kDomSchedule, threadIdx.x, (uint32_t)((s + 1) >> 32),
+                                              d.key0, d.key1);
+                uint32_t *o = sched + 12u * ((i + 1u) & 1u) + 4u * threadIdx.x;
+                o[0] = w.x;
+                o[1] = w.y;
+                o[2] = w.z;
+                o[3] = w.w;
+            }
+            for (uint32_t t = threadIdx.x; t < tasks; t += blockDim.x) word_task<Q, Barrier>(lat, f, t, s_tab, s_trans, tr);
+            __syncthreads();
+        }
+    }
+}
+
+// MaxThreads = 512 serves blocks of up to 512 threads (measured faster: the
+// compiler schedules for fewer waves per SIMD), 1024 the largest blocks.
+template <int MaxThreads>
+__global__ void __launch_bounds__(MaxThreads) k_sweep_lds_w(BatchArgs args)
+{
+    constexpr bool kBarrier = MaxThreads > 512;
+    __shared__ uint2 s_tab[kDevTabEntries];
+    __shared__ uint2 s_trans[kTransEntries];
+    __shared__ uint32_t sched[24];
+    extern __shared__ uint32_t lat[];
+    uint8_t *scr = args.scratch[blockIdx.x];
+    const LatDesc d = *(const LatDesc *)(scr + kScrDesc);
+    const uint32_t my_sweeps = args.sweeps[blockIdx.x];
+    if (threadIdx.x < 3) {
+        const uint64_t s = d.next_sweep;
+        const u32x4 w = philox4x32_10((uint32_t)s, kDomSchedule, threadIdx.x, (uint32_t)(s >> 32), d.key0, d.key1);
+        sched[4 * threadIdx.x] = w.x;
+        sched[4 * threadIdx.x + 1] = w.y;
+        sched[4 * threadIdx.x + 2] = w.z;
+        sched[4 * threadIdx.x + 3] = w.w;
+    }
+    LdsGeom g;
+    g.L = d.L;
+    g.Lq = d.L >> 2;
+    g.H = d.L >> 1;
+    g.Wp = d.L >> 6;
+    g.csz = (uint32_t)g.H * g.Wp;
+    stage_lattice(lat, d, g);
+    stage_tables(s_tab, s_trans, (const uint2 *)(scr + kScrDevTab), (const uint2 *)(scr + kScrTrans));
+
+    // threads per a-word: the largest Q <= 8 with Q * (a-words) <= block size
+    const uint32_t words = g.csz;
+    int Q = 1;
+    while (Q < 8 && words * (uint32_t)(2 * Q) <= blockDim.x) Q *= 2;
+    int tr[3] = {0, 0, 0};
+    switch (Q) {
+    case 1: word_sweeps<1, kBarrier>(lat, sched, d, my_sweeps, s_tab, s_trans, tr); break;
+    case 2: word_sweeps<2, kBarrier>(lat, sched, d, my_sweeps, s_tab, s_trans, tr); break;
+    case 4: word_sweeps<4, kBarrier>(lat, sched, d, my_sweeps, s_tab, s_trans, tr); break;
+    default: word_sweeps<8, kBarrier>(lat, sched, d, my_sweeps, s_tab, s_trans, tr); break;
+    }
+    unstage_lattice(lat, d, g);
     if (threadIdx.x == 0) ((LatDesc *)(scr + kScrDesc))->next_sweep = d.next_sweep + my_sweeps;
     block_reduce_add<3>(tr, (unsigned long long *)(scr + kScrTrackBase));
 }
@@ -882,21 +1111,34 @@ hipError_t launch_observables(uint8_t *scratch, const void *state, int L, int en
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_lds(const BatchArgs &a, int max_L, int threads, hipStream_t s)
+hipError_t init_kernel_attributes()
 {
-    const uint32_t calls = (uint32_t)max_L * (uint32_t)max_L / 16u;
-    uint32_t block = calls < 1024u ? ((calls + 63u) / 64u) * 64u : 1024u;
+    // allow more than the default 64 KiB of dynamic LDS (L = 512 needs 64 KiB + tables)
+    const int bytes = (int)(lds_state_words(kLdsMaxL) * 4u);
+    hipError_t e = hipFuncSetAttribute((const void *)k_sweep_lds, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_sweep_lds_w<512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_sweep_lds_w<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return e;
+}
+
+hipError_t launch_sweep_lds(const BatchArgs &a, int max_L, int threads, bool word, hipStream_t s)
+{
+    // default block: per-site form, one thread per Philox call (two pairs);
+    // word form, two threads per a-word (at least 256)
+    const uint32_t sq = (uint32_t)max_L * (uint32_t)max_L;
+    const uint32_t units = word ? std::max(256u, sq / 64u) : sq / 16u;
+    uint32_t block = units < 1024u ? ((units + 63u) / 64u) * 64u : 1024u;
     if (threads > 0) block = (uint32_t)std::min(1024, std::max(64, threads / 64 * 64));
     if (block < 64u) block = 64u;
     const size_t lds = lds_state_words(max_L) * 4u;
-    static bool attr_set = false;
-    if (!attr_set) {
-        // allow more than the default 64 KiB of dynamic LDS (L = 512 needs 64 KiB + tables)
-        (void)hipFuncSetAttribute((const void *)k_sweep_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(lds_state_words(kLdsMaxL) * 4u));
-        attr_set = true;
-    }
-    hipLaunchKernelGGL(k_sweep_lds, dim3((unsigned)a.count), dim3(block), lds, s, a);
+    if (word && block <= 512u)
+        hipLaunchKernelGGL(k_sweep_lds_w<512>, dim3((unsigned)a.count), dim3(block), lds, s, a);
+    else if (word)
+        hipLaunchKernelGGL(k_sweep_lds_w<1024>, dim3((unsigned)a.count), dim3(block), lds, s, a);
+    else
+        hipLaunchKernelGGL(k_sweep_lds, dim3((unsigned)a.count), dim3(block), lds, s, a);
     return hipGetLastError();
 }
 

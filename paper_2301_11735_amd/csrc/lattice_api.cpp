@@ -375,21 +375,29 @@ int pinned_batch_threads()
 // Returns the block size to use (0 = default) and, while tuning, events to
 // record around the launch plus a slot for batch_threads_done, which waits
 // for that launch (the first calls for a new shape are therefore blocking).
-int batch_threads_for(int max_L, int count, hipStream_t stream, hipEvent_t *start, hipEvent_t *stop, int *slot)
+int batch_threads_for(int max_L, int count, bool word, hipStream_t stream, hipEvent_t *start, hipEvent_t *stop,
+                      int *slot)
 {
     (void)stream;
     *start = *stop = nullptr;
     *slot = -1;
     if (const int pinned = pinned_batch_threads()) return pinned;
-    const int calls = max_L * max_L / 16;
     int bucket = 1;
     while (bucket < count) bucket *= 2;
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    const auto key = std::make_pair(max_L, bucket);
+    const auto key = std::make_pair(max_L | (word ? 1 << 20 : 0), bucket);
     TuneEntry &t = g_tune[key];
     if (t.candidates.empty()) {
-        for (int c : {1024, 512, 256})
-            if (c <= 1024 && (c / 2 < calls || c == 256)) t.candidates.push_back(c);
+        if (word) {
+            // at most 8 threads per a-word are used
+            const int words = max_L * max_L / 128;
+            for (int c : {1024, 512, 256, 128})
+                if (c <= std::max(128, 8 * words) && (c >= 256 || words <= 128)) t.candidates.push_back(c);
+        } else {
+            const int calls = max_L * max_L / 16;
+            for (int c : {1024, 512, 256})
+                if (c / 2 < calls || c == 256) t.candidates.push_back(c);
+        }
         t.ns_per_update.assign(t.candidates.size(), -1.0);
     }
     if (t.best >= 0) return t.candidates[t.best];
@@ -428,26 +436,56 @@ void batch_threads_done(int slot, double site_updates)
     }
 }
 
+// The tuned block size for a batch shape if tuning has finished, else 0
+// (the default); never launches anything.
+int batch_threads_tuned(int max_L, int count, bool word)
+{
+    if (const int pinned = pinned_batch_threads()) return pinned;
+    int bucket = 1;
+    while (bucket < count) bucket *= 2;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune.find(std::make_pair(max_L | (word ? 1 << 20 : 0), bucket));
+    return it != g_tune.end() && it->second.best >= 0 ? it->second.candidates[(size_t)it->second.best] : 0;
+}
+
+int enqueue_observables_batch(lattice *const *hs, int32_t count, unsigned long long *dev, hipStream_t stream)
+{
+    for (int32_t b = 0; b < count; b += kMaxBatch) {
+        BatchArgs a{};
+        a.count = std::min<int32_t>(kMaxBatch, count - b);
+        for (int i = 0; i < a.count; ++i) a.scratch[i] = hs[b + i]->d_scratch;
+        const hipError_t e = launch_observables_batch(a, dev + 10 * (size_t)b, stream);
+        if (e != hipSuccess) return hip_fail(e, "batched observables launch");
+    }
+    return LAT_OK;
+}
+
 // Batched path: lattices resident in LDS, up to kMaxBatch per launch.
 int enqueue_lds_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps, uint32_t uniform,
-                       hipStream_t stream)
+                       hipStream_t stream, bool tune)
 {
+    // LATTICE_LDS_SITE=1 keeps every batch on the per-site form (tests compare the two)
+    const char *env = std::getenv("LATTICE_LDS_SITE");
+    const bool force_site = env && env[0] == '1';
     for (int32_t b = 0; b < count; b += kMaxBatch) {
         BatchArgs a{};
         a.count = std::min<int32_t>(kMaxBatch, count - b);
         int max_L = 0;
         double updates = 0;
+        bool word = !force_site;
         for (int i = 0; i < a.count; ++i) {
             a.scratch[i] = hs[b + i]->d_scratch;
             a.sweeps[i] = sweeps ? sweeps[b + i] : uniform;
             max_L = std::max(max_L, hs[b + i]->L);
             updates += (double)hs[b + i]->N * a.sweeps[i];
+            word = word && hs[b + i]->L % 64 == 0;
         }
-        hipEvent_t t0, t1;
-        int slot;
-        const int threads = batch_threads_for(max_L, a.count, stream, &t0, &t1, &slot);
+        hipEvent_t t0 = nullptr, t1 = nullptr;
+        int slot = -1;
+        const int threads = tune ? batch_threads_for(max_L, a.count, word, stream, &t0, &t1, &slot)
+                                 : batch_threads_tuned(max_L, a.count, word);
         if (t0) (void)hipEventRecord(t0, stream);
-        const hipError_t e = launch_sweep_lds(a, max_L, threads, stream);
+        const hipError_t e = launch_sweep_lds(a, max_L, threads, word, stream);
         if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
         if (t1) {
             (void)hipEventRecord(t1, stream);
@@ -551,6 +589,12 @@ int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void 
     build_threshold_table(p->Delta, p->V, p->J, p->T, tab);
     build_device_table(tab, dev_tab);
     build_transition_table(trans);
+    {
+        static std::once_flag once;
+        static hipError_t init_err = hipSuccess;
+        std::call_once(once, [] { init_err = init_kernel_attributes(); });
+        if (init_err != hipSuccess) return hip_fail(init_err, "kernel set-up");
+    }
 
     lattice *h = new lattice();
     h->L = p->L;
@@ -641,14 +685,8 @@ int lattice_observables_batch(lattice *const *hs, int32_t count, void *d_out, si
     for (int32_t i = 0; i < count; ++i)
         if (!live(hs[i])) return fail(LAT_ESTATE, "null or destroyed handle in batch");
     hipStream_t stream = (hipStream_t)hip_stream;
-    unsigned long long *dev = (unsigned long long *)d_out;
-    for (int32_t b = 0; b < count; b += kMaxBatch) {
-        BatchArgs a{};
-        a.count = std::min<int32_t>(kMaxBatch, count - b);
-        for (int i = 0; i < a.count; ++i) a.scratch[i] = hs[b + i]->d_scratch;
-        const hipError_t e = launch_observables_batch(a, dev + 10 * (size_t)b, stream);
-        if (e != hipSuccess) return hip_fail(e, "batched observables launch");
-    }
+    const int rc = enqueue_observables_batch(hs, count, (unsigned long long *)d_out, stream);
+    if (rc) return rc;
     std::vector<int64_t> v((size_t)count * 10);
     hipError_t e = hipSuccess;
     if (count > 0) e = hipMemcpyAsync(v.data(), d_out, v.size() * 8, hipMemcpyDeviceToHost, stream);

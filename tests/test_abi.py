@@ -93,3 +93,22 @@ def test_calls_on_null_handles_fail_cleanly():
     assert L.lattice_observables(None, ctypes.byref(lat.LatObs())) == lat.LAT_ESTATE
     assert L.lattice_sweep_batch(None, 1, 1, None) == lat.LAT_EINVAL
     assert L.lattice_sweep_batch(None, 0, 1, None) == lat.LAT_OK
+
+
+def test_batch_graph_rejects_bad_arguments_without_a_device():
+    L = lat.lib()
+    vp = ctypes.c_void_p
+    h = vp()
+    d = ctypes.c_void_p(16)  # never dereferenced: every call below fails before any device work
+    assert L.lattice_batch_graph_create(None, 1, 1, 1, None, 80, None, None) == lat.LAT_EINVAL
+    assert L.lattice_batch_graph_create(None, 0, 1, 1, None, 80, None, ctypes.byref(h)) == lat.LAT_EINVAL
+    assert h.value is None
+    fake = (vp * 1)(None)
+    assert L.lattice_batch_graph_create(fake, 1, 0, 1, d, 80, None, ctypes.byref(h)) == lat.LAT_EINVAL
+    assert L.lattice_batch_graph_create(fake, 1, 5, 0, d, 80, None, ctypes.byref(h)) == lat.LAT_EINVAL
+    assert L.lattice_batch_graph_create(fake, 1, 5, 1, d, 79, None, ctypes.byref(h)) == lat.LAT_ENOMEM
+    assert L.lattice_batch_graph_create(fake, 1, 5, 3, d, 239, None, ctypes.byref(h)) == lat.LAT_ENOMEM
+    assert L.lattice_batch_graph_create(fake, 1, 5, 3, d, 240, None, ctypes.byref(h)) == lat.LAT_ESTATE
+    assert L.lattice_batch_graph_launch(None, 1) == lat.LAT_ESTATE
+    assert L.lattice_batch_graph_read(None, ctypes.byref(lat.LatObs())) == lat.LAT_ESTATE
+    assert L.lattice_batch_graph_destroy(None) == lat.LAT_ESTATE

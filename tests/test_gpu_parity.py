@@ -315,3 +315,103 @@ def test_autotuned_batch_launch_shapes_match_oracle():
         for s, g, o in zip(specs, gs, os_):
             o.sweeps(k)
             assert np.array_equal(g.read_state(), o.codes), f"call {call} L={s.L}"
+
+
+def _word_batch_specs():
+    rng = np.random.default_rng(17)
+    out = []
+    for i, (L, enc) in enumerate([(64, 0), (64, 1), (128, 1), (192, 1), (256, 0), (320, 1), (512, 1)]):
+        out.append(SMALL.with_(L=L, encoding=enc, seed=1300 + i, n=float(rng.uniform(-0.3, 0.3)),
+                               Delta=float(rng.uniform(-1, 1)), V=float(rng.uniform(-1, 1)),
+                               T=float(rng.uniform(0.2, 2.5))))
+    return out
+
+
+@pytest.mark.parametrize("threads", [128, 256, 512, 1024])
+def test_word_batch_every_block_size_matches_oracle(threads, monkeypatch):
+    """Batches whose lattices all have L % 64 == 0 take the word-parallel LDS
+    kernel; the block size sets how many threads share an a-word (1 to 8),
+    per lattice.  Every split must give the oracle's chain bit for bit,
+    including int8 lattices and class rows of 1, 2, 3, 4, 5 and 8 words."""
+    monkeypatch.setenv("LATTICE_BATCH_THREADS", str(threads))
+    _say(f"case word batch threads={threads}")
+    specs = _word_batch_specs()
+    gs = [_make(s) for s in specs]
+    os_ = [_oracle(s) for s in specs]
+    obs = lat.BatchObservables(len(gs))
+    for k in (3, 2):
+        lat.sweep_batch(gs, k)
+        for o in os_:
+            o.sweeps(k)
+        got = obs(gs)
+        for s, g, o, go in zip(specs, gs, os_, got):
+            assert np.array_equal(g.read_state(), o.codes), f"threads={threads} L={s.L} enc={s.encoding}"
+            assert go.ints() == o.observables().tolist()
+            assert [go.track_nD, go.track_nV, go.track_nJ] == o.track.tolist()
+    for g in gs:
+        g.destroy()
+
+
+def test_word_and_site_batch_forms_agree(monkeypatch):
+    """The per-site LDS kernel (forced) and the word-parallel one give the
+    same states and trackers over 40 sweeps."""
+    _say("case word vs site forms")
+    specs = _word_batch_specs()
+    monkeypatch.setenv("LATTICE_LDS_SITE", "1")
+    site = [_make(s) for s in specs]
+    lat.sweep_batch(site, 40)
+    site_obs = lat.BatchObservables(len(site))(site)
+    monkeypatch.delenv("LATTICE_LDS_SITE")
+    word = [_make(s) for s in specs]
+    lat.sweep_batch(word, 40)
+    word_obs = lat.BatchObservables(len(word))(word)
+    for s, a, b, oa, ob in zip(specs, site, word, site_obs, word_obs):
+        assert np.array_equal(a.read_state(), b.read_state()), f"L={s.L}"
+        assert oa.as_dict() == ob.as_dict()
+
+
+@pytest.mark.parametrize("kind", ["word", "site"])
+def test_batch_graph_replays_match_eager_and_oracle(kind):
+    """Observation intervals captured into a HIP graph: every replay (with
+    eager batched work and synchronisation in between) leaves the lattices and
+    every interval's observables exactly where the same eager calls do, and
+    where the oracle does."""
+    _say(f"case batch graph {kind}")
+    if kind == "word":
+        specs = _word_batch_specs()
+    else:
+        specs = [SMALL.with_(L=L, encoding=enc, seed=1400 + i, T=0.3 + 0.4 * i)
+                 for i, (L, enc) in enumerate([(12, 0), (64, 1), (100, 0), (128, 1)])]
+    every, intervals = 4, 3
+    glats = [_make(s) for s in specs]
+    elats = [_make(s) for s in specs]
+    os_ = [_oracle(s) for s in specs]
+    obs = lat.BatchObservables(len(elats))
+    graph = lat.BatchGraph(glats, every, intervals)
+    total = 0
+    for rep, times in enumerate([1, 1, 2, 1]):
+        graph.launch(times)
+        got = graph.read()
+        exp = []
+        for _ in range(times):
+            exp = []
+            for k in range(intervals):
+                lat.sweep_batch(elats, every)
+                exp.append(obs(elats))
+        total += every * intervals * times
+        for k in range(intervals):
+            for s, a, b in zip(specs, got[k], exp[k]):
+                assert a.as_dict() == b.as_dict(), f"replay {rep} interval {k} L={s.L}"
+                assert a.sweep == total - every * (intervals - 1 - k)
+        for s, g, e, o, a in zip(specs, glats, elats, os_, got[-1]):
+            o.sweeps(every * intervals * times)
+            assert np.array_equal(g.read_state(), e.read_state()), f"replay {rep} L={s.L}"
+            assert np.array_equal(g.read_state(), o.codes), f"replay {rep} L={s.L}"
+            assert a.ints() == o.observables().tolist()
+            assert [a.track_nD, a.track_nV, a.track_nJ] == o.track.tolist()
+    graph.destroy()
+    # the lattices carry on eagerly from where the graph left them
+    lat.sweep_batch(glats, 3)
+    for g, o in zip(glats, os_):
+        o.sweeps(3)
+        assert np.array_equal(g.read_state(), o.codes)
