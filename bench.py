@@ -44,11 +44,17 @@ BYTES_PER_SITE_UPDATE_2BIT = 0.5
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_phase_2bit_L8192_traffic.txt")
 
 
+PHASE_KERNEL_SOURCES = ("phase.hip", "device_common.h", "kernels.h", "philox.h")
+
+
 def kernel_source_digest() -> str:
+    """SHA-256 over the sources the phase kernel is compiled from."""
     import hashlib
 
-    path = os.path.join(ROOT, "paper_2301_11735_amd", "csrc", "kernels.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for name in PHASE_KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2301_11735_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic():
@@ -61,7 +67,7 @@ def measured_traffic():
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernels_hip_sha256") != kernel_source_digest():
+    if vals.get("phase_sources_sha256") != kernel_source_digest():
         return None
     try:
         return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
@@ -105,7 +111,8 @@ def write_traffic_summary(fetch_csv, write_csv, cfetch_csv, cwrite_csv, out=TRAF
         f"# phase dispatches: fetch {len(f)}, write {len(w)}",
         f"# FETCH_SIZE mean {statistics.mean(f):.1f} min {min(f):.1f} max {max(f):.1f}; copy factor {ff:.4f}",
         f"# WRITE_SIZE mean {statistics.mean(w):.1f} min {min(w):.1f} max {max(w):.1f}; copy factor {fw:.4f}",
-        f"kernels_hip_sha256={kernel_source_digest()}",
+        f"# phase_sources_sha256 covers csrc/{', csrc/'.join(PHASE_KERNEL_SOURCES)}",
+        f"phase_sources_sha256={kernel_source_digest()}",
         f"fetch_bytes_per_launch={fetch_b:.0f}",
         f"write_bytes_per_launch={write_b:.0f}",
     ]

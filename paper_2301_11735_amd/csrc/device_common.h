@@ -1,0 +1,220 @@
+// Device helpers shared by the gfx950 kernels of the coupled-pair Metropolis
+// sweep (arXiv:2301.11735, section 3.1 update, section 3.2 parallel form):
+// table staging, the per-pair step, neighbour sums 16 sites at a time, the
+// on-device schedule and block reductions.  Included by the .hip sources only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+#include "philox.h"
+
+namespace lat {
+namespace {
+
+constexpr uint32_t kM5 = 0x55555555u;  // bit 0 of every 2-bit field
+constexpr uint32_t kM3 = 0x33333333u;  // low 2 bits of every nibble
+constexpr uint32_t kM0F = 0x0F0F0F0Fu; // low nibble of every byte
+
+constexpr int charge_c(int c) { return (c & 2) ? 1 - 2 * (c & 1) : 0; }
+
+// Number of configurations k_q of the same-charge set for every pair state
+// (3 bits per state): 6 for q = 0, 4 for q = +-1, and 1 for the frozen
+// |q| = 2 states, whose single entry is the null move.
+constexpr uint64_t make_kq()
+{
+    uint64_t v = 0;
+    for (int st = 0; st < 16; ++st) {
+        const int q = charge_c(st & 3) + charge_c(st >> 2);
+        const uint64_t kq = (q == 2 || q == -2) ? 1 : (q == 0 ? 6 : 4);
+        v |= kq << (3 * st);
+    }
+    return v;
+}
+constexpr uint64_t kKq = make_kq();
+
+__device__ __forceinline__ void stage_tables(uint2 *s_tab, uint2 *s_trans, const uint2 *__restrict__ g_tab,
+                                             const uint2 *__restrict__ g_trans)
+{
+    for (int i = threadIdx.x; i < kDevTabEntries; i += blockDim.x) s_tab[i] = g_tab[i];
+    for (int i = threadIdx.x; i < kTransEntries; i += blockDim.x) s_trans[i] = g_trans[i];
+    __syncthreads();
+}
+
+// One coupled-pair Metropolis step (section 3.1).  bpack holds the neighbour
+// sums (sumS_a+4, sumS_b+4, sumsig_a+4, sumsig_b+4) as bytes; uc picks the
+// configuration j = floor(k_q * (uc >> 8) / 2^24); ua is the acceptance draw,
+// compared as min(ua, 2^32-2) < thr so that the reserved "always" threshold
+// 2^32-1 accepts every draw.  Returns the new pair state and adds the
+// accepted move's packed triple to `packed`.
+__device__ __forceinline__ uint32_t pair_step(uint32_t st, uint32_t bpack, uint32_t uc, uint32_t ua,
+                                              const uint2 *__restrict__ s_trans, const uint2 *__restrict__ s_tab,
+                                              uint32_t &packed)
+{
+    const uint32_t kq = (uint32_t)(kKq >> (3u * st)) & 7u;
+    const uint32_t j = ((uc >> 8) * kq) >> 24;
+    const uint2 tr = s_trans[st * 6u + j];
+    const int idx = __builtin_amdgcn_sdot4((int)tr.x, (int)bpack, (int)(tr.y & 0xFFFFu), false);
+    const uint2 e = s_tab[idx];
+    const bool acc = min(ua, 0xFFFFFFFEu) < e.x;
+    packed += acc ? e.y : 0u;
+    return acc ? (tr.y >> 16) : st;
+}
+
+// Per-thread tracker: counts and biased sums of the accepted triples.
+__device__ __forceinline__ void unpack_tracker(uint32_t packed, int (&tr)[3])
+{
+    const int cnt = (int)(packed >> 27);
+    tr[0] += (int)((packed >> 20) & 127u) - 2 * cnt;
+    tr[1] += (int)((packed >> 10) & 1023u) - 16 * cnt;
+    tr[2] += (int)(packed & 1023u) - 16 * cnt;
+}
+
+template <int K, typename T>
+__device__ __forceinline__ void block_reduce_add(T (&v)[K], unsigned long long *dst)
+{
+    __shared__ T part[16][K];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < K; ++i) part[wave][i] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            long long s = 0;
+            for (int w = 0; w < nw; ++w) s += (long long)part[w][i];
+            if (s != 0) atomicAdd(&dst[i], (unsigned long long)s);
+        }
+    }
+}
+
+// Neighbour contribution of a code c to the packed sums: byte 0 (a side) or
+// byte 1 (b side) gets 1+S(c), byte 2 or byte 3 gets 1+sigma(c); the values
+// per code are the bytes of kVS = {1,1,2,0} and kVG = {2,0,1,1}.
+constexpr uint32_t kVS = 0x00020101u;
+constexpr uint32_t kVG = 0x01010002u;
+__device__ __forceinline__ uint32_t contrib_a(uint32_t c) { return __builtin_amdgcn_perm(kVG, kVS, 0x0C040C00u + c * 0x00010001u); }
+__device__ __forceinline__ uint32_t contrib_b(uint32_t c) { return __builtin_amdgcn_perm(kVG, kVS, 0x040C000Cu + c * 0x01000100u); }
+
+// Schedule of sweep s (same definition as the host's): r in {1,2,3};
+// phase p has D_p = (r + 4 m_p, 1 + 2 k_p).
+__device__ __forceinline__ void device_schedule(int L, uint32_t k0, uint32_t k1, uint64_t s, int &r, int (&m)[4],
+                                                int (&k)[4])
+{
+    uint32_t Wd[12];
+#pragma unroll
+    for (uint32_t t = 0; t < 3; ++t) {
+        const u32x4 w = philox4x32_10((uint32_t)s, kDomSchedule, t, (uint32_t)(s >> 32), k0, k1);
+        Wd[4 * t] = w.x;
+        Wd[4 * t + 1] = w.y;
+        Wd[4 * t + 2] = w.z;
+        Wd[4 * t + 3] = w.w;
+    }
+    r = 1 + (int)(((Wd[0] >> 8) * 3u) >> 24);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        m[p] = (int)mulhi_u32(Wd[1 + 2 * p], (uint32_t)(L / 4));
+        k[p] = (int)mulhi_u32(Wd[2 + 2 * p], (uint32_t)(L / 2));
+    }
+}
+
+// 16 sites of the class row at word offset `row` of `st`, starting at class
+// position xs (periodic).  32-bit offsets keep the base pointer uniform.
+__device__ __forceinline__ uint32_t load16(const uint32_t *__restrict__ st, uint32_t row, int W, int xs)
+{
+    const int jw = xs >> 4, sh = xs & 15;
+    const uint32_t w0 = st[row + (uint32_t)jw];
+    const uint32_t w1 = st[row + (uint32_t)(jw + 1 == W ? 0 : jw + 1)];
+    return sh ? __builtin_amdgcn_alignbit(w1, w0, 2u * (uint32_t)sh) : w0;
+}
+
+// Neighbour sums of 16 sites from their 4 neighbour words, SWAR: per code
+// the values 1+S in {0,1,2} and 1+sigma in {0,1,2} as 2-bit fields, split
+// into even and odd sites so that the 4-term sums (at most 8) fit nibbles.
+struct SideSums {
+    uint32_t ES, OS, EG, OG;  // nibble u: sum over neighbours of site 2u (E) or 2u+1 (O)
+};
+
+__device__ __forceinline__ SideSums side_sums(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3)
+{
+    SideSums s{0u, 0u, 0u, 0u};
+    const uint32_t ws[4] = {w0, w1, w2, w3};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t h = (ws[i] >> 1) & kM5, l = ws[i] & kM5;
+        const uint32_t vS = ((h & ~l) << 1) | (h ^ kM5);        // code 2 -> 2, 3 -> 0, spins -> 1
+        const uint32_t vG = (((h | l) ^ kM5) << 1) | h;          // code 0 -> 2, 1 -> 0, charges -> 1
+        s.ES += vS & kM3;
+        s.OS += (vS >> 2) & kM3;
+        s.EG += vG & kM3;
+        s.OG += (vG >> 2) & kM3;
+    }
+    return s;
+}
+
+// 4x4 byte transpose: out[k] = (r0.byte k, r1.byte k, r2.byte k, r3.byte k).
+__device__ __forceinline__ void transpose4(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t r3, uint32_t &c0,
+                                           uint32_t &c1, uint32_t &c2, uint32_t &c3)
+{
+    const uint32_t p01lo = __builtin_amdgcn_perm(r1, r0, 0x05010400u);
+    const uint32_t p01hi = __builtin_amdgcn_perm(r1, r0, 0x07030602u);
+    const uint32_t p23lo = __builtin_amdgcn_perm(r3, r2, 0x05010400u);
+    const uint32_t p23hi = __builtin_amdgcn_perm(r3, r2, 0x07030602u);
+    c0 = __builtin_amdgcn_perm(p23lo, p01lo, 0x05040100u);
+    c1 = __builtin_amdgcn_perm(p23lo, p01lo, 0x07060302u);
+    c2 = __builtin_amdgcn_perm(p23hi, p01hi, 0x05040100u);
+    c3 = __builtin_amdgcn_perm(p23hi, p01hi, 0x07060302u);
+}
+
+// (r0.byte k, r1.byte k, r2.byte k, r3.byte k) with sel = k | (4 + k) << 8 | 0x0C0C0000.
+__device__ __forceinline__ uint32_t gather_byte(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t r3, uint32_t sel)
+{
+    const uint32_t lo = __builtin_amdgcn_perm(r1, r0, sel);
+    const uint32_t hi = __builtin_amdgcn_perm(r3, r2, sel);
+    return __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+}
+
+// Observable sums: sum S, sum S^2, bonds S S, bonds sigma sigma, sum sigma,
+// staggered sigma, staggered S.  Bonds (x,y)-(x+1,y) and (x,y)-(x,y+1).
+__device__ __forceinline__ int spin_of(uint32_t c) { return (c & 2u) ? 0 : 1 - 2 * (int)(c & 1u); }
+__device__ __forceinline__ int charge_of(uint32_t c) { return (c & 2u) ? 1 - 2 * (int)(c & 1u) : 0; }
+
+// Block-level sum of K values written (not added) to dst[0..K): no atomics.
+template <int K, typename T>
+__device__ __forceinline__ void block_reduce_store(T (&v)[K], long long *dst)
+{
+    __shared__ long long part[16][K];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < K; ++i) part[wave][i] = (long long)v[i];
+    __syncthreads();
+    if (threadIdx.x < K) {
+        const int nw = (blockDim.x + 63) >> 6;
+        long long s = 0;
+        for (int w = 0; w < nw; ++w) s += part[w][threadIdx.x];
+        dst[threadIdx.x] = s;
+    }
+}
+
+// Bond sums of 16 sites (h, l bit planes) with 16 partner sites (hp, lp):
+// S S = +1 for equal charges, -1 for opposite; sigma sigma likewise for spins.
+__device__ __forceinline__ void bond_sums(uint32_t h, uint32_t l, uint32_t hp, uint32_t lp, int &bSS, int &bss)
+{
+    const uint32_t diff = l ^ lp;
+    const uint32_t cc = h & hp, mm = (h | hp) ^ kM5;  // both charged / both spins
+    bSS += __popc(cc & ~diff) - __popc(cc & diff);
+    bss += __popc(mm & ~diff) - __popc(mm & diff);
+}
+
+}  // namespace
+}  // namespace lat

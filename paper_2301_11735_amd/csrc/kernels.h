@@ -1,5 +1,5 @@
 // Launch interface between the host API (lattice_api.cpp) and the gfx950
-// kernels (kernels.hip).  C++ linkage, library-internal.
+// kernels (phase.hip, obs.hip, batch.hip).  C++ linkage, library-internal.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -4,7 +4,8 @@
 // configuration (section 3.1), the FP64 Metropolis threshold table (section
 // 3.1, eq. 3), the per-sweep schedule of non-interacting pairs (section 3.2)
 // and the layout conversion between canonical codes and the device encodings.
-// All sweep and reduction work runs in the kernels of kernels.hip.
+// All sweep and reduction work runs in the kernels of phase.hip, obs.hip and
+// batch.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
