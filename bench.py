@@ -120,6 +120,54 @@ def write_traffic_summary(fetch_csv, write_csv, cfetch_csv, cwrite_csv, out=TRAF
     print("\n".join(lines))
 
 
+def write_counter_summary(out_md, csvs, trace_stats=None):
+    """Per-dispatch means of every counter in the given rocprofv3 --pmc CSVs,
+    per kernel, as a markdown table, with the derived per-site figures of the
+    L=8192 phase kernel."""
+    import csv
+    import re
+    import statistics
+    from collections import defaultdict
+
+    vals = defaultdict(lambda: defaultdict(list))
+    for path in csvs:
+        for r in csv.DictReader(open(path)):
+            name = re.sub(r"\(.*", "", r["Kernel_Name"].replace("lat::(anonymous namespace)::", "").replace("void ", ""))
+            vals[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    lines = ["| kernel | counter | dispatches | mean per dispatch |", "|---|---|---|---|"]
+    keep = ("k_phase_2bit", "k_sweep_lds_w", "k_obs_2bit", "k_obs_batch", "k_fold_sums")
+    for k in sorted(v for v in vals if v.startswith(keep)):
+        for c in sorted(vals[k]):
+            v = vals[k][c]
+            lines.append(f"| {k} | {c} | {len(v)} | {statistics.mean(v):.6g} |")
+    ph = vals.get("k_phase_2bit<1>", {})
+    if "SQ_INSTS_VALU" in ph:
+        n_updates = workloads.LARGE.L ** 2 / 4
+        insts = statistics.mean(ph["SQ_INSTS_VALU"])
+        lines += ["", f"k_phase_2bit at L={workloads.LARGE.L}: one dispatch updates N/4 = {n_updates:.0f} sites.",
+                  f"* VALU wave-instructions per dispatch: {insts:.4g}; lane-ops per site update "
+                  f"(x64 lanes): {insts * 64 / n_updates:.1f}"]
+        if "SQ_INSTS_LDS" in ph:
+            lines.append(f"* LDS instructions per site update (wave-instr x64 / updates): "
+                         f"{statistics.mean(ph['SQ_INSTS_LDS']) * 64 / n_updates:.2f}")
+        if "SQ_LDS_BANK_CONFLICT" in ph and "SQ_LDS_IDX_ACTIVE" in ph:
+            lines.append(f"* SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE: "
+                         f"{statistics.mean(ph['SQ_LDS_BANK_CONFLICT']) / max(1.0, statistics.mean(ph['SQ_LDS_IDX_ACTIVE'])):.3f}")
+        if "SQ_WAIT_INST_LDS" in ph and "SQ_WAVE_CYCLES" in ph:
+            lines.append(f"* SQ_WAIT_INST_LDS / SQ_WAVE_CYCLES: "
+                         f"{statistics.mean(ph['SQ_WAIT_INST_LDS']) / statistics.mean(ph['SQ_WAVE_CYCLES']):.4f}")
+        if "TCC_HIT_sum" in ph and "TCC_MISS_sum" in ph:
+            hit, miss = statistics.mean(ph["TCC_HIT_sum"]), statistics.mean(ph["TCC_MISS_sum"])
+            lines.append(f"* L2 hit rate: {hit / (hit + miss):.3f}")
+        if trace_stats:
+            us = float(trace_stats)
+            lines.append(f"* VALU issue utilisation at 2.4 GHz over the traced {us:.2f} us average: "
+                         f"{insts * 4 / (1024 * us * 1e-6 * 2.4e9):.3f} (a wave64 VALU instruction occupies a "
+                         f"16-lane SIMD for 4 cycles; 1024 SIMDs)")
+    open(out_md, "a").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +179,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="0 skips the served run")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only copy a device buffer of this many MiB 3 times (HBM counter calibration) and exit")
+    ap.add_argument("--counter-summary", nargs="+", metavar=("OUT_MD", "CSV"),
+                    help="write per-kernel means of rocprofv3 --pmc counter_collection.csv files to OUT_MD and exit")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="write the traffic summary from four rocprofv3 --pmc counter_collection.csv files and exit")
     return ap.parse_args()
@@ -259,6 +309,11 @@ def main():
     args = parse()
     if args.traffic_summary:
         write_traffic_summary(*args.traffic_summary)
+        return
+    if args.counter_summary:
+        out_md, *rest = args.counter_summary
+        us = os.environ.get("PHASE_KERNEL_TRACE_US")
+        write_counter_summary(out_md, rest, us)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (run with --gpus 1)",
