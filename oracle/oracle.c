@@ -31,6 +31,10 @@
  *       paper's random maps (section 3.2);
  *   R6  randomness is Philox4x32-10 keyed by the seed, with the counter
  *       naming the sweep, the phase and the pair.
+ *   R12 map mode (section 3.2 as printed): maps of max(1, floor(N/10))
+ *       pairs built by the paper's sequential algorithm, the site draws
+ *       taken from Philox words in counter order; a pair's two sites may be
+ *       neighbours.
  */
 #include <math.h>
 #include <stdint.h>
@@ -77,6 +81,8 @@ static void philox_seeded(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
 #define DOM_SCHEDULE 0x100u
 #define DOM_INIT     0x200u
 #define DOM_GENERAL  0x300u
+#define DOM_MAP      0x400u
+#define DOM_MAPSTEP  0x500u
 
 static uint32_t mulhi32(uint32_t a, uint32_t b)
 {
@@ -410,6 +416,101 @@ int orc_series(int32_t L, double Delta, double V, double J, double T, uint64_t s
 {
     for (uint64_t k = 0; k < n_obs; ++k) {
         int rc = orc_sweeps(L, Delta, V, J, T, seed, start_sweep + k * every, every, codes, track);
+        if (rc) return rc;
+        orc_observables(L, codes, &series[7 * k]);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Map mode (section 3.2, "Algorithm for building a map" and the processing
+ * of maps).  A map is a list of coupled pairs no two of which interact: no
+ * site of one pair is a site or a nearest neighbour of a site of another. */
+
+/* Pairs per map: N/10 (section 3.2), at least one. */
+int64_t orc_map_pairs(int32_t L)
+{
+    int64_t n = (int64_t)L * L / 10;
+    return n < 1 ? 1 : n;
+}
+
+/* Build map m.  The paper's steps: start with every site unmarked; draw a
+ * site at random until an unmarked one comes up, mark it (site a); the same
+ * for site b; add the pair (a, b); mark the nearest neighbours of a and of b;
+ * repeat until the map holds orc_map_pairs(L) pairs.
+ * Draw k of map m is site mulhi(w, N) with w = word (k mod 4) of the Philox
+ * counter (m_lo, DOM_MAP, floor(k/4), m_hi).  Writes pairs[2i] = a_i and
+ * pairs[2i+1] = b_i; returns the number of draws consumed, or -1 if L < 3. */
+int64_t orc_map_build(int32_t L, uint64_t seed, uint64_t m, int64_t *pairs)
+{
+    if (L < 3) return -1;
+    const int64_t N = (int64_t)L * L, n_pairs = orc_map_pairs(L);
+    uint8_t *marked = (uint8_t *)calloc((size_t)N, 1);
+    if (!marked) return -1;
+    uint64_t k = 0;
+    uint32_t w[4] = {0, 0, 0, 0};
+    for (int64_t i = 0; i < n_pairs; ++i) {
+        int64_t site[2];
+        for (int h = 0; h < 2; ++h) {
+            for (;;) {
+                if ((k & 3u) == 0)
+                    philox_seeded(seed, (uint32_t)m, DOM_MAP, (uint32_t)(k >> 2), (uint32_t)(m >> 32), w);
+                const int64_t cand = (int64_t)mulhi32(w[k & 3u], (uint32_t)N);
+                ++k;
+                if (!marked[cand]) {
+                    marked[cand] = 1;
+                    site[h] = cand;
+                    break;
+                }
+            }
+        }
+        pairs[2 * i] = site[0];
+        pairs[2 * i + 1] = site[1];
+        for (int h = 0; h < 2; ++h) {
+            int64_t nb[4];
+            neighbours(L, site[h], nb);
+            for (int d = 0; d < 4; ++d) marked[nb[d]] = 1;
+        }
+    }
+    free(marked);
+    return (int64_t)k;
+}
+
+/* Map steps start_map .. start_map + n_maps - 1: build each map, then apply
+ * one coupled-pair Metropolis step to each of its pairs in map order.  Pair i
+ * of map m uses Philox counter (m_lo, DOM_MAPSTEP, floor(i/2), m_hi): words
+ * h and h+1 with h = 2*(i mod 2) are the configuration and acceptance draws.
+ * The pairs of a map do not interact, so any order gives the same result. */
+int orc_map_steps(int32_t L, double Delta, double V, double J, double T, uint64_t seed,
+                  uint64_t start_map, uint64_t n_maps, int8_t *codes, int64_t track[3])
+{
+    if (L < 3) return -1;
+    const int64_t n_pairs = orc_map_pairs(L);
+    int64_t *pairs = (int64_t *)malloc((size_t)(2 * n_pairs) * sizeof(int64_t));
+    if (!pairs) return -1;
+    for (uint64_t m = start_map; m < start_map + n_maps; ++m) {
+        if (orc_map_build(L, seed, m, pairs) < 0) {
+            free(pairs);
+            return -1;
+        }
+        for (int64_t i = 0; i < n_pairs; ++i) {
+            uint32_t w[4];
+            philox_seeded(seed, (uint32_t)m, DOM_MAPSTEP, (uint32_t)(i >> 1), (uint32_t)(m >> 32), w);
+            const int h = 2 * (int)(i & 1);
+            pair_step(L, codes, pairs[2 * i], pairs[2 * i + 1], w[h], w[h + 1], Delta, V, J, T, track);
+        }
+    }
+    free(pairs);
+    return 0;
+}
+
+/* Same for the map mode; one observation every `every` maps. */
+int orc_map_series(int32_t L, double Delta, double V, double J, double T, uint64_t seed,
+                   uint64_t start_map, uint64_t every, uint64_t n_obs, int8_t *codes,
+                   int64_t track[3], int64_t *series)
+{
+    for (uint64_t k = 0; k < n_obs; ++k) {
+        int rc = orc_map_steps(L, Delta, V, J, T, seed, start_map + k * every, every, codes, track);
         if (rc) return rc;
         orc_observables(L, codes, &series[7 * k]);
     }

@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import test_oracle_maps as maps
 from tests import test_oracle_model as model
 from tests import test_oracle_stats as stats
 
@@ -64,6 +65,19 @@ def _pin_charge_target():
         model.test_charge_target(L, n, Q, Nc)
 
 
+def _pin_map_structure():
+    for L in (8, 10, 16):
+        maps.test_map_pairs_never_interact(L)
+
+
+def _pin_map_adjacency():
+    maps.test_map_first_site_uniform_and_partner_may_be_adjacent()
+
+
+def _pin_map_chain():
+    maps.test_map_mode_matches_exact_enumeration(4, 2, 1.0)
+
+
 MUTANTS = [
     ("J/4 coefficient of eq. (3) dropped", "0.25 * J * nJ", "J * nJ", _pin_4x4),
     ("bond a-b counted twice for adjacent pairs", "if (nb[k] == a) continue;", ";", _pin_pair_delta),
@@ -81,6 +95,18 @@ MUTANTS = [
      _pin_charge_target),
     ("general-mode partner may equal the first site", "uint32_t b = bp + (bp >= a ? 1u : 0u);",
      "uint32_t b = bp;", _pin_3x3),
+    ("map: neighbours of the partner not marked", "for (int h = 0; h < 2; ++h) {\n            int64_t nb[4];",
+     "for (int h = 0; h < 1; ++h) {\n            int64_t nb[4];", _pin_map_structure),
+    ("map: only three neighbours marked", "for (int d = 0; d < 4; ++d) marked[nb[d]] = 1;",
+     "for (int d = 0; d < 3; ++d) marked[nb[d]] = 1;", _pin_map_structure),
+    ("map: a drawn site is not checked for a mark", "if (!marked[cand]) {", "if (1) {", _pin_map_structure),
+    ("map: N/11 pairs instead of N/10", "int64_t n = (int64_t)L * L / 10;", "int64_t n = (int64_t)L * L / 11;",
+     _pin_map_structure),
+    ("map: partner drawn only among sites not adjacent to the first", "site[h] = cand;\n                    break;",
+     "site[h] = cand;\n                    if (h == 0) { int64_t q[4]; neighbours(L, cand, q); "
+     "for (int d = 0; d < 4; ++d) marked[q[d]] = 1; }\n                    break;", _pin_map_adjacency),
+    ("map step: a pair's configuration drawn with the acceptance word", "pairs[2 * i + 1], w[h], w[h + 1],",
+     "pairs[2 * i + 1], w[h + 1], w[h + 1],", _pin_map_chain),
 ]
 
 
