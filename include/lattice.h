@@ -226,6 +226,28 @@ int lat_server_stats(lat_server *s, lat_server_counters *out);
 /* Destroy the server and any resident lattices (caller memory untouched). */
 int lat_server_destroy(lat_server *s);
 
+/* Map mode (section 3.2 as the paper builds it): apply maps first_map ..
+ * first_map + n_maps - 1.  Map m of a lattice is a list of max(1, N/10)
+ * coupled pairs built with the paper's sequential algorithm from the
+ * lattice's seed: draw a site until an unmarked one comes up (site a), the
+ * same for its partner b, record (a, b), mark the neighbours of both, repeat.
+ * Draw k of map m is site floor(w * N / 2^32), w being word k mod 4 of
+ * Philox4x32-10 at counter (m_lo, 0x400, k / 4, m_hi) with the seed as key.
+ * No two pairs of a map interact, so they are updated concurrently; a and b
+ * may be neighbours, and the bond between them then enters the energy change
+ * once.  Pair i of the map takes words 2(i mod 2) (configuration) and
+ * 2(i mod 2)+1 (acceptance) of Philox at counter (m_lo, 0x500, i / 2, m_hi).
+ * Maps are built on the device; the lattice must have L <= 256.  The sweep
+ * counter of the handle is not changed.  Asynchronous on the handle's stream.
+ * Errors: LAT_ESTATE, LAT_EINVAL (L > 256), LAT_EHIP. */
+int lattice_map_steps(lattice *h, uint64_t first_map, uint32_t n_maps);
+/* The same for `count` lattices in one launch (one block per lattice, up to
+ * 256 per launch), on hip_stream.  Each lattice uses its own seed, so its
+ * maps are its own.  Errors: LAT_EINVAL (bad batch, duplicate, L > 256),
+ * LAT_ESTATE, LAT_EHIP. */
+int lattice_map_steps_batch(lattice *const *hs, int32_t count, uint64_t first_map, uint32_t n_maps,
+                            void *hip_stream);
+
 /* Release the handle (host memory only; caller buffers are untouched). */
 int lattice_destroy(lattice *h);
 

@@ -32,6 +32,8 @@ EXPORTS = (
     "lattice_batch_graph_launch",
     "lattice_batch_graph_read",
     "lattice_batch_graph_destroy",
+    "lattice_map_steps",
+    "lattice_map_steps_batch",
     "lattice_destroy",
     "lattice_last_error",
     "lat_server_create",
@@ -153,6 +155,10 @@ def lib() -> ctypes.CDLL:
         L.lattice_batch_graph_read.restype = ctypes.c_int
         L.lattice_batch_graph_destroy.argtypes = [vp]
         L.lattice_batch_graph_destroy.restype = ctypes.c_int
+        L.lattice_map_steps.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint32]
+        L.lattice_map_steps.restype = ctypes.c_int
+        L.lattice_map_steps_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32, vp]
+        L.lattice_map_steps_batch.restype = ctypes.c_int
         L.lattice_destroy.argtypes = [vp]
         L.lattice_destroy.restype = ctypes.c_int
         L.lat_server_create.argtypes = [vp, sz, ctypes.c_int32, ctypes.c_uint64, vp, ctypes.POINTER(vp)]
@@ -246,6 +252,10 @@ class Lattice:
     def sweep(self, sweeps: int = 1):
         _check(lib().lattice_sweep(self.handle, sweeps))
 
+    def map_steps(self, first_map: int, n_maps: int = 1):
+        """Apply maps first_map .. first_map+n_maps-1 of the map mode."""
+        _check(lib().lattice_map_steps(self.handle, first_map, n_maps))
+
     def observables(self) -> LatObs:
         o = LatObs()
         _check(lib().lattice_observables(self.handle, ctypes.byref(o)))
@@ -270,6 +280,12 @@ class Lattice:
 
 def _handles(lattices):
     return (ctypes.c_void_p * len(lattices))(*[lat.handle.value for lat in lattices])
+
+
+def map_steps_batch(lattices, first_map: int, n_maps: int, stream=None):
+    """Apply maps first_map .. first_map+n_maps-1 (map mode) to several lattices in one call."""
+    _check(lib().lattice_map_steps_batch(_handles(lattices), len(lattices), first_map, n_maps,
+                                         _stream_handle(stream)))
 
 
 def sweep_batch(lattices, sweeps: int, stream=None):

@@ -50,7 +50,8 @@ constexpr size_t kScrObsSlots = 9216;                 // kMaxObsSlots x 7 x int6
 constexpr int kMaxObsSlots = 256;
 constexpr size_t kScrSlots = 24576;                   // kMaxSlots x 3 x int64 from the phase kernels
 constexpr int kMaxSlots = 1024;
-constexpr size_t kScrBytes = kScrSlots + (size_t)kMaxSlots * 24;  // 49152
+constexpr size_t kScrFullTab = kScrSlots + (size_t)kMaxSlots * 24;  // 49152: kTabSize x uint32 thresholds
+constexpr size_t kScrBytes = kScrFullTab + ((size_t)kTabSize * 4 + 255) / 256 * 256;  // 71168
 
 // Per-lattice descriptor kept in the lattice's scratch, read by the batched
 // kernel.  next_sweep is advanced on the device by every path that sweeps.
@@ -109,6 +110,25 @@ hipError_t launch_zero_i64(unsigned long long *p, int n, hipStream_t s);
 hipError_t launch_observables(uint8_t *scratch, const void *state, int L, int encoding, hipStream_t s);
 // Batched kernel; dynamic LDS is sized for the largest L.  threads = block
 // size (a multiple of 64, at most 1024; 0 = min(1024, N/16 of the largest L)).
+// Map mode (section 3.2 random maps): lattices with L <= kMapMaxL, one block
+// per lattice holding the codes (one byte per site), the map's mark bitmap,
+// its pair list and the full threshold table in LDS.
+constexpr int kMapMaxL = 256;
+constexpr int kMapThreads = 256;
+struct MapArgs {
+    int count;
+    uint8_t *scratch[kMaxBatch];
+    uint32_t first_map_lo, first_map_hi, n_maps;
+};
+// LDS bytes one block needs for a lattice of side L.
+inline size_t map_lds_bytes(int L)
+{
+    const size_t N = (size_t)L * L, pairs = N / 10 < 1 ? 1 : N / 10;
+    return (size_t)kTabSize * 4 + (N + 3) / 4 * 4 + (N + 31) / 32 * 4 + pairs * 4 + 256 * 4;
+}
+hipError_t launch_map_steps(const MapArgs &a, int max_L, hipStream_t s);
+hipError_t init_map_kernel_attributes();
+
 // One-time kernel set-up (dynamic LDS limits); called before the first launch.
 hipError_t init_kernel_attributes();
 // Batched sweeps with each lattice resident in LDS.  word = every lattice of

@@ -593,7 +593,10 @@ int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void 
     {
         static std::once_flag once;
         static hipError_t init_err = hipSuccess;
-        std::call_once(once, [] { init_err = init_kernel_attributes(); });
+        std::call_once(once, [] {
+            init_err = init_kernel_attributes();
+            if (init_err == hipSuccess) init_err = init_map_kernel_attributes();
+        });
         if (init_err != hipSuccess) return hip_fail(init_err, "kernel set-up");
     }
 
@@ -633,6 +636,8 @@ int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void 
                            h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->d_scratch + kScrTrans, trans.data(), trans.size() * 4, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->d_scratch + kScrFullTab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->d_scratch + kScrDesc, &desc, sizeof(desc), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = launch_zero_i64((unsigned long long *)(h->d_scratch + kScrTrack), 11, h->stream);

@@ -18,6 +18,7 @@ hipError_t launch_zero_i64(unsigned long long *, int, hipStream_t) { return hipS
 hipError_t launch_observables(uint8_t *, const void *, int, int, hipStream_t) { return hipSuccess; }
 hipError_t launch_sweep_lds(const BatchArgs &, int, int, bool, hipStream_t) { return hipSuccess; }
 hipError_t init_kernel_attributes() { return hipSuccess; }
+hipError_t init_map_kernel_attributes() { return hipSuccess; }
 hipError_t launch_advance(LatDesc *, uint32_t, hipStream_t) { return hipSuccess; }
 bool persistent_2bit_supported(int, const Tuning2Bit &, int *, int *) { return false; }
 hipError_t launch_sweeps_2bit(const PhaseArgs &, const Tuning2Bit &, uint32_t, unsigned *, unsigned *, hipStream_t)
