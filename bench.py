@@ -176,6 +176,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-maps", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="0 skips the served run")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only copy a device buffer of this many MiB 3 times (HBM counter calibration) and exit")
@@ -286,6 +287,29 @@ def batched_run(torch, lat, b2b_sample: int = 8, b2b_sweeps: int = 1000) -> dict
         }
         out["batched_over_back_to_back"] = out["site_updates_per_s"] / b2b
     return out
+
+
+def map_run(torch, lat, n_maps: int = 100) -> dict:
+    """Map mode (the paper's random maps, built on the device) on the batched
+    workload's 256 lattices of L=128: n_maps maps each in one launch."""
+    specs = workloads.batched_specs()
+    lats = [lat.Lattice(s.L, s.n, s.Delta, s.V, s.J, s.T, s.seed, encoding=s.encoding) for s in specs]
+    lat.map_steps_batch(lats, 0, 2)  # warm-up (not counted)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.map_steps_batch(lats, 2, n_maps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for g in lats:
+        g.destroy()
+    pairs = max(1, specs[0].L ** 2 // 10)
+    updates = len(specs) * n_maps * 2 * pairs
+    return {
+        "workload": f"256 lattices L=128 2-bit (the batched workload), {n_maps} maps of {pairs} pairs each, one launch",
+        "maps_per_s": len(specs) * n_maps / dt,
+        "site_updates_per_s": updates / dt,
+        "seconds": dt,
+    }
 
 
 def served_run(seconds: float) -> dict:
@@ -412,6 +436,8 @@ def main():
     g.destroy()
     if not args.no_batched:
         line["batched"] = batched_run(torch, lat)
+    if not args.no_maps:
+        line["map_mode"] = map_run(torch, lat)
     if args.serve_seconds > 0:
         line["served"] = served_run(args.serve_seconds)
     if not args.no_cpu_baseline:
