@@ -124,7 +124,7 @@ struct MapArgs {
 inline size_t map_lds_bytes(int L)
 {
     const size_t N = (size_t)L * L, pairs = N / 10 < 1 ? 1 : N / 10;
-    return (size_t)kTabSize * 4 + (N + 3) / 4 * 4 + (N + 31) / 32 * 4 + pairs * 4 + 256 * 4;
+    return (size_t)kTabSize * 4 + (N + 3) / 4 * 4 + (N + 31) / 32 * 4 + pairs * 4;
 }
 hipError_t launch_map_steps(const MapArgs &a, int max_L, hipStream_t s);
 hipError_t init_map_kernel_attributes();

@@ -6,7 +6,7 @@
 //   2. wave 0 builds the map with the paper's sequential algorithm -- draw a
 //      site until an unmarked one comes up, mark it; the same for the
 //      partner; record the pair; mark the neighbours of both -- its 64 lanes
-//      computing the next 256 site draws at once and lane 0 taking them in
+//      computing the next 256 site draws at once and the wave taking them in
 //      draw order;
 //   3. all threads apply one coupled-pair Metropolis step (section 3.1) to the
 //      map's pairs in parallel.  No two pairs of a map interact, so this equals
@@ -45,48 +45,60 @@ __device__ __forceinline__ void site_neighbours(int L, uint32_t s, uint32_t (&nb
 
 __device__ __forceinline__ void mark(uint32_t *bitmap, uint32_t s) { bitmap[s >> 5] |= 1u << (s & 31u); }
 
-// Map m into pairs[] (a | b << 16), by wave 0 of the block.
-__device__ void build_map(uint32_t *bitmap, uint32_t *pairs, uint32_t *cbuf, int L, uint32_t N, uint32_t n_pairs,
-                          uint32_t m_lo, uint32_t m_hi, uint32_t key0, uint32_t key1)
+// Map m into pairs[] (a | b << 16), by wave 0 of the block.  Per round the
+// 64 lanes compute the next 256 site draws, their neighbours and whether each
+// was already marked when the round began (one ballot per draw slot); then the
+// wave walks the draws in draw order with uniform control flow: a draw marked
+// at the start of the round is rejected without touching LDS, any other is
+// checked against the live bitmap (a broadcast LDS read, which the in-order LDS
+// queue orders after the marks already issued).  Marks are LDS atomic ors.
+__device__ void build_map(uint32_t *bitmap, uint32_t *pairs, int L, uint32_t N, uint32_t n_pairs, uint32_t m_lo,
+                          uint32_t m_hi, uint32_t key0, uint32_t key1)
 {
     const uint32_t lane = threadIdx.x;
     uint32_t k = 0, count = 0, need_b = 0, a_site = 0;
+    uint32_t an[4] = {0u, 0u, 0u, 0u};  // neighbours of the pending first site
     while (count < n_pairs) {
-        // draws k .. k+255: draw d is word d mod 4 of Philox call d / 4
+        // draws k .. k+255: draw d is word d mod 4 of Philox call d / 4, held by lane d / 4
         const u32x4 w = philox4x32_10(m_lo, kDomMap, (k >> 2) + lane, m_hi, key0, key1);
-        cbuf[4 * lane] = mulhi_u32(w.x, N);
-        cbuf[4 * lane + 1] = mulhi_u32(w.y, N);
-        cbuf[4 * lane + 2] = mulhi_u32(w.z, N);
-        cbuf[4 * lane + 3] = mulhi_u32(w.w, N);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (lane == 0) {
-            for (uint32_t q = 0; q < 256u && count < n_pairs; ++q) {
-                const uint32_t c = cbuf[q];
-                const uint32_t bit = 1u << (c & 31u);
-                const uint32_t word = bitmap[c >> 5];
-                if (word & bit) continue;
-                bitmap[c >> 5] = word | bit;
+        const uint32_t c[4] = {mulhi_u32(w.x, N), mulhi_u32(w.y, N), mulhi_u32(w.z, N), mulhi_u32(w.w, N)};
+        uint32_t nbv[4][4];
+        uint64_t pre[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            site_neighbours(L, c[q], nbv[q]);
+            pre[q] = __ballot((bitmap[c[q] >> 5] >> (c[q] & 31u)) & 1u);
+        }
+        for (int l = 0; l < 64 && count < n_pairs; ++l) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (count >= n_pairs || ((pre[q] >> l) & 1u)) continue;
+                const uint32_t site = (uint32_t)__builtin_amdgcn_readlane((int)c[q], l);
+                const uint32_t word = (uint32_t)__builtin_amdgcn_readfirstlane((int)bitmap[site >> 5]);
+                if (word & (1u << (site & 31u))) continue;
+                if (lane == 0) atomicOr(&bitmap[site >> 5], 1u << (site & 31u));
                 if (!need_b) {
-                    a_site = c;
+                    a_site = site;
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) an[d] = (uint32_t)__builtin_amdgcn_readlane((int)nbv[q][d], l);
                     need_b = 1;
                 } else {
-                    pairs[count++] = a_site | (c << 16);
-                    uint32_t nb[4];
-                    site_neighbours(L, a_site, nb);
-                    for (int d = 0; d < 4; ++d) mark(bitmap, nb[d]);
-                    site_neighbours(L, c, nb);
-                    for (int d = 0; d < 4; ++d) mark(bitmap, nb[d]);
+                    if (lane == 0) {
+                        pairs[count] = a_site | (site << 16);
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) atomicOr(&bitmap[an[d] >> 5], 1u << (an[d] & 31u));
+                    }
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        const uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int)nbv[q][d], l);
+                        if (lane == 0) atomicOr(&bitmap[t >> 5], 1u << (t & 31u));
+                    }
+                    ++count;
                     need_b = 0;
                 }
             }
         }
-        count = (uint32_t)__builtin_amdgcn_readfirstlane((int)count);
         k += 256u;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -152,7 +164,6 @@ __global__ void __launch_bounds__(kMapThreads) k_map_steps(MapArgs args)
     uint8_t *codes = (uint8_t *)(smem + kTabSize);          // N bytes
     uint32_t *bitmap = smem + kTabSize + (N + 3u) / 4u;     // ceil(N/32) words
     uint32_t *pairs = bitmap + (N + 31u) / 32u;             // n_pairs
-    uint32_t *cbuf = pairs + n_pairs;                       // 256 draws
 
     const uint32_t *g_thr = (const uint32_t *)(scr + kScrFullTab);
     for (uint32_t i = threadIdx.x; i < (uint32_t)kTabSize; i += blockDim.x) thr[i] = g_thr[i];
@@ -178,7 +189,7 @@ __global__ void __launch_bounds__(kMapThreads) k_map_steps(MapArgs args)
         const uint32_t m_lo = (uint32_t)m, m_hi = (uint32_t)(m >> 32);
         for (uint32_t i = threadIdx.x; i < (N + 31u) / 32u; i += blockDim.x) bitmap[i] = 0u;
         __syncthreads();
-        if (threadIdx.x < 64) build_map(bitmap, pairs, cbuf, L, N, n_pairs, m_lo, m_hi, d.key0, d.key1);
+        if (threadIdx.x < 64) build_map(bitmap, pairs, L, N, n_pairs, m_lo, m_hi, d.key0, d.key1);
         __syncthreads();
         // pairs 2c and 2c+1 share Philox call c
         for (uint32_t c = threadIdx.x; 2u * c < n_pairs; c += blockDim.x) {
