@@ -340,6 +340,15 @@ class BatchGraph:
         flat = list(out)
         return [flat[k * n:(k + 1) * n] for k in range(self.intervals)]
 
+    def read_array(self):
+        """The same records as a numpy structured array of shape (intervals, lattices)."""
+        import numpy as np
+
+        n = len(self._lats)
+        out = (LatObs * (n * self.intervals))()
+        _check(lib().lattice_batch_graph_read(self._h, out))
+        return np.ctypeslib.as_array(out).reshape(self.intervals, n)
+
     def destroy(self):
         if self._h:
             _check(lib().lattice_batch_graph_destroy(self._h))

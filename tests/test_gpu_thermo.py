@@ -1,0 +1,87 @@
+"""GPU temperature scans (paper_2301_11735_amd.thermo) on 4x4 lattices against
+exact results: the fixed-charge sector by exact enumeration (tests/exact),
+and the Delta -> infinity, n = 0 limit (an antiferromagnetic Ising model with
+J_eff = J/4) by enumerating all 2^16 spin states here.  Estimates are means
+over 64 independent replicas; the bar is |z| < 4 with a 1% allowance for the
+finite-series bias of the per-replica variance estimators.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2301_11735_amd import thermo
+from tests import exact
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _close(name, est, err, ref, T):
+    z = (est - ref) / max(err, 1e-12)
+    assert abs(est - ref) < 4 * err + 0.01 * abs(ref), f"T={T} {name}: {est:.6f} +- {err:.6f} vs exact {ref:.6f} (z={z:.2f})"
+
+
+def test_scan_4x4_matches_exact_enumeration():
+    L, N, Q = 4, 16, 2
+    Delta, V, J, n = 0.25, 0.5, 1.0, 0.125
+    temps = [0.5, 1.0, 2.0]
+    _say("case thermo 4x4 sector scan")
+    rows = thermo.scan(L, n, Delta, V, J, temps, replicas=64, sweeps=8000, burn=500, every=1, seed0=700)
+    for row in rows:
+        ex = exact.sector_averages(L, Q, Delta, V, J, row["T"])
+        _close("e", row["e"], row["e_err"], ex["E"] / N, row["T"])
+        _close("C", row["C"], row["C_err"], ex["C"], row["T"])
+        _close("nc", row["nc"], row["nc_err"], ex["Nc"] / N, row["T"])
+
+
+def _ising_4x4(J_eff, T):
+    L, N = 4, 16
+    states = np.arange(1 << N, dtype=np.int64)
+    sig = 1 - 2 * ((states[:, None] >> np.arange(N)) & 1)
+    idx = np.arange(N).reshape(L, L)
+    right = np.roll(idx, -1, axis=1).reshape(-1)
+    down = np.roll(idx, -1, axis=0).reshape(-1)
+    bonds = (sig * sig[:, right]).sum(axis=1) + (sig * sig[:, down]).sum(axis=1)
+    E = J_eff * bonds
+    stag = 1 - 2 * ((np.arange(N) // L + np.arange(N) % L) % 2)
+    M = sig.sum(axis=1)
+    Ms = (sig * stag).sum(axis=1)
+    w = np.exp(-(E - E.min()) / T)
+    Z = w.sum()
+    avg = lambda X: float((w * X).sum() / Z)  # noqa: E731
+    return {"e": avg(E) / N, "C": (avg(E * E) - avg(E) ** 2) / (N * T * T),
+            "chi": avg(M * M) / (N * T), "chi_st": avg(Ms * Ms) / (N * T)}
+
+
+@pytest.mark.parametrize("T", [1.0, 2.0])
+def test_scan_ising_limit_4x4_matches_enumeration(T):
+    L, J = 4, 1.0
+    _say(f"case thermo 4x4 Ising limit T={T}")
+    row, = thermo.scan(L, 0.0, 1e6, 0.5, J, [T], replicas=64, sweeps=8000, burn=500, every=1, seed0=900,
+                       n_charged=0)
+    assert row["nc"] == 0.0
+    ex = _ising_4x4(0.25 * J, T)
+    for name in ("e", "C", "chi", "chi_st"):
+        _close(name, row[name], row[name + "_err"], ex[name], T)
+
+
+def test_heat_capacity_curve_4x4_matches_exact():
+    """C(T) of the 4x4 sector n = 1/8 across the range where the exact curve has
+    its structure; prints the table (T, C from 64 replicas, exact C)."""
+    L, N, Q = 4, 16, 2
+    Delta, V, J, n = 0.25, 0.5, 1.0, 0.125
+    temps = [0.25, 0.35, 0.5, 0.7, 1.0, 1.4, 2.0, 3.0]
+    _say("case thermo 4x4 C(T) curve")
+    rows = thermo.scan(L, n, Delta, V, J, temps, replicas=64, sweeps=8000, burn=500, every=1, seed0=1100)
+    _say("T  C_gpu  C_err  C_exact  e_gpu  e_err  e_exact")
+    for row in rows:
+        ex = exact.sector_averages(L, Q, Delta, V, J, row["T"])
+        _say(f"{row['T']:.2f} {row['C']:.5f} {row['C_err']:.5f} {ex['C']:.5f} "
+             f"{row['e']:.5f} {row['e_err']:.5f} {ex['E'] / N:.5f}")
+        _close("C", row["C"], row["C_err"], ex["C"], row["T"])
+        _close("e", row["e"], row["e_err"], ex["E"] / N, row["T"])
