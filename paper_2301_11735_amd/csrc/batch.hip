@@ -203,13 +203,15 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
 
     const uint32_t call0 = (uint32_t)Y * (uint32_t)(Lq >> 1) + 8u * (uint32_t)j;
     uint32_t dA = 0u, dB = 0u, packed = 0u;
+    const uint32_t kq2w = word_kq2(A0, B0);
     auto do_call = [&](int c, uint32_t be, uint32_t bo) {
         const u32x4 w = philox4x32_10(f.s_lo, (uint32_t)f.p, call0 + (uint32_t)c, f.s_hi, f.key0, f.key1);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int t = 2 * c + h;
             const uint32_t s0 = ((A0 >> (2 * t)) & 3u) | (((B0 >> (2 * t)) & 3u) << 2);
-            const uint32_t ns = pair_step(s0, h ? bo : be, h ? w.z : w.x, h ? w.w : w.y, s_trans, s_tab, packed);
+            const uint32_t ns = pair_step_k2(s0, (kq2w >> (2 * t)) & 3u, h ? bo : be, h ? w.z : w.x, h ? w.w : w.y,
+                                             s_trans, s_tab, packed);
             const uint32_t dd = ns ^ s0;
             dA |= (dd & 3u) << (2 * t);
             dB |= (dd >> 2) << (2 * t);

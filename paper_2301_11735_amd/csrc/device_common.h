@@ -19,20 +19,34 @@ constexpr uint32_t kM0F = 0x0F0F0F0Fu; // low nibble of every byte
 
 constexpr int charge_c(int c) { return (c & 2) ? 1 - 2 * (c & 1) : 0; }
 
-// Number of configurations k_q of the same-charge set for every pair state
-// (3 bits per state): 6 for q = 0, 4 for q = +-1, and 1 for the frozen
-// |q| = 2 states, whose single entry is the null move.
-constexpr uint64_t make_kq()
+// Half the number of configurations k_q of the same-charge set, for every
+// pair state st = code_a | code_b << 2 (2 bits per state): 3 for q = 0
+// (k_q = 6), 2 for q = +-1 (k_q = 4), and 0 for the frozen |q| = 2 states,
+// whose configuration index is then always 0 (their single entry is the null
+// move).  j = floor(k_q u / 2^24) = floor((k_q/2) u / 2^23) for the 24-bit u.
+constexpr uint32_t make_kq2()
 {
-    uint64_t v = 0;
+    uint32_t v = 0;
     for (int st = 0; st < 16; ++st) {
         const int q = charge_c(st & 3) + charge_c(st >> 2);
-        const uint64_t kq = (q == 2 || q == -2) ? 1 : (q == 0 ? 6 : 4);
-        v |= kq << (3 * st);
+        const uint32_t k2 = (q == 2 || q == -2) ? 0u : (q == 0 ? 3u : 2u);
+        v |= k2 << (2 * st);
     }
     return v;
 }
-constexpr uint64_t kKq = make_kq();
+constexpr uint32_t kKq2 = make_kq2();
+
+// k_q/2 of the 16 pairs of an aligned (a-word, b-word) couple, 2 bits per
+// pair at the pairs' own bit positions: a pair is frozen when both sites are
+// charges of one sign, has k_q = 4 when exactly one site is charged, and
+// k_q = 6 otherwise.
+__device__ __forceinline__ uint32_t word_kq2(uint32_t A, uint32_t B)
+{
+    const uint32_t ha = (A >> 1) & kM5, la = A & kM5, hb = (B >> 1) & kM5, lb = B & kM5;
+    const uint32_t frozen = ha & hb & ~(la ^ lb);
+    const uint32_t one = ha ^ hb;
+    return (~(one | frozen) & kM5) | ((~frozen & kM5) << 1);
+}
 
 __device__ __forceinline__ void stage_tables(uint2 *s_tab, uint2 *s_trans, const uint2 *__restrict__ g_tab,
                                              const uint2 *__restrict__ g_trans)
@@ -48,18 +62,24 @@ __device__ __forceinline__ void stage_tables(uint2 *s_tab, uint2 *s_trans, const
 // compared as min(ua, 2^32-2) < thr so that the reserved "always" threshold
 // 2^32-1 accepts every draw.  Returns the new pair state and adds the
 // accepted move's packed triple to `packed`.
-__device__ __forceinline__ uint32_t pair_step(uint32_t st, uint32_t bpack, uint32_t uc, uint32_t ua,
-                                              const uint2 *__restrict__ s_trans, const uint2 *__restrict__ s_tab,
-                                              uint32_t &packed)
+__device__ __forceinline__ uint32_t pair_step_k2(uint32_t st, uint32_t kq2, uint32_t bpack, uint32_t uc, uint32_t ua,
+                                                 const uint2 *__restrict__ s_trans, const uint2 *__restrict__ s_tab,
+                                                 uint32_t &packed)
 {
-    const uint32_t kq = (uint32_t)(kKq >> (3u * st)) & 7u;
-    const uint32_t j = ((uc >> 8) * kq) >> 24;
+    const uint32_t j = ((uc >> 8) * kq2) >> 23;
     const uint2 tr = s_trans[st * 6u + j];
     const int idx = __builtin_amdgcn_sdot4((int)tr.x, (int)bpack, (int)(tr.y & 0xFFFFu), false);
     const uint2 e = s_tab[idx];
     const bool acc = min(ua, 0xFFFFFFFEu) < e.x;
     packed += acc ? e.y : 0u;
     return acc ? (tr.y >> 16) : st;
+}
+
+__device__ __forceinline__ uint32_t pair_step(uint32_t st, uint32_t bpack, uint32_t uc, uint32_t ua,
+                                              const uint2 *__restrict__ s_trans, const uint2 *__restrict__ s_tab,
+                                              uint32_t &packed)
+{
+    return pair_step_k2(st, (kKq2 >> (2u * st)) & 3u, bpack, uc, ua, s_trans, s_tab, packed);
 }
 
 // Per-thread tracker: counts and biased sums of the accepted triples.

@@ -167,6 +167,7 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
         // 2c+1, so calls 0,2,4,6 need planes 0 and 1, calls 1,3,5,7 planes 2
         // and 3; handling them in that order keeps 8 packed words live.
         uint32_t Anew = 0u, Bnew = 0u, packed = 0u;
+        const uint32_t kq2w = word_kq2(cur.A0, cur.B0);
         const uint32_t call0 = (uint32_t)Y * (uint32_t)(Lq >> 1) + 8u * (uint32_t)j;
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
@@ -185,8 +186,8 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
                 for (int h = 0; h < 2; ++h) {
                     const int t = 2 * c + h;
                     const uint32_t s0 = ((cur.A0 >> (2 * t)) & 3u) | (((cur.B0 >> (2 * t)) & 3u) << 2);
-                    const uint32_t ns = pair_step(s0, h ? go[k] : ge[k], h ? w.z : w.x, h ? w.w : w.y, s_trans,
-                                                  s_tab, packed);
+                    const uint32_t ns = pair_step_k2(s0, (kq2w >> (2 * t)) & 3u, h ? go[k] : ge[k], h ? w.z : w.x,
+                                                     h ? w.w : w.y, s_trans, s_tab, packed);
                     Anew |= (ns & 3u) << (2 * t);
                     Bnew |= (ns >> 2) << (2 * t);
                 }
