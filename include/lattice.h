@@ -227,26 +227,36 @@ int lat_server_stats(lat_server *s, lat_server_counters *out);
 int lat_server_destroy(lat_server *s);
 
 /* Map mode (section 3.2 as the paper builds it): apply maps first_map ..
- * first_map + n_maps - 1.  Map m of a lattice is a list of max(1, N/10)
+ * first_map + n_maps - 1.  Map m of a lattice is a list of non-interacting
  * coupled pairs built with the paper's sequential algorithm from the
- * lattice's seed: draw a site until an unmarked one comes up (site a), the
- * same for its partner b, record (a, b), mark the neighbours of both, repeat.
- * Draw k of map m is site floor(w * N / 2^32), w being word k mod 4 of
+ * lattice's seed.  Draw k of map m is the word w = word k mod 4 of
  * Philox4x32-10 at counter (m_lo, 0x400, k / 4, m_hi) with the seed as key.
- * No two pairs of a map interact, so they are updated concurrently; a and b
- * may be neighbours, and the bond between them then enters the energy change
- * once.  Pair i of the map takes words 2(i mod 2) (configuration) and
- * 2(i mod 2)+1 (acceptance) of Philox at counter (m_lo, 0x500, i / 2, m_hi).
- * Maps are built on the device; the lattice must have L <= 256.  The sweep
- * counter of the handle is not changed.  Asynchronous on the handle's stream.
- * Errors: LAT_ESTATE, LAT_EINVAL (L > 256), LAT_EHIP. */
-int lattice_map_steps(lattice *h, uint64_t first_map, uint32_t n_maps);
+ *   partner = LAT_MAP_ANY (the paper's algorithm): max(1, N/10) pairs; a
+ *     draw gives site floor(w N / 2^32); draw until an unmarked site comes up
+ *     (site a, marked), the same for its partner b, record (a, b), mark the
+ *     neighbours of both, repeat.  a and b may be neighbours; the bond
+ *     between them then enters the energy change once.
+ *   partner = LAT_MAP_NEIGHBOUR (the paper's first version, kept to show its
+ *     loss of ergodicity): max(1, N/20) pairs; a draw gives a; if a is marked
+ *     the next draw starts over, else the next draw picks b = neighbour
+ *     w >> 30 of a (order x+1, x-1, y+1, y-1); if b is marked the pair is
+ *     dropped, else a, b and the neighbours of both are marked and (a, b)
+ *     is recorded.
+ * No two pairs of a map interact, so they are updated concurrently.  Pair i
+ * of the map takes words 2(i mod 2) (configuration) and 2(i mod 2)+1
+ * (acceptance) of Philox at counter (m_lo, 0x500, i / 2, m_hi).  Maps are
+ * built on the device; the lattice must have L <= 256.  The sweep counter of
+ * the handle is not changed.  Asynchronous on the handle's stream.
+ * Errors: LAT_ESTATE, LAT_EINVAL (L > 256, unknown partner rule), LAT_EHIP. */
+#define LAT_MAP_ANY 0
+#define LAT_MAP_NEIGHBOUR 1
+int lattice_map_steps(lattice *h, uint64_t first_map, uint32_t n_maps, int32_t partner);
 /* The same for `count` lattices in one launch (one block per lattice, up to
  * 256 per launch), on hip_stream.  Each lattice uses its own seed, so its
- * maps are its own.  Errors: LAT_EINVAL (bad batch, duplicate, L > 256),
- * LAT_ESTATE, LAT_EHIP. */
+ * maps are its own.  Errors: LAT_EINVAL (bad batch, duplicate, L > 256,
+ * unknown partner rule), LAT_ESTATE, LAT_EHIP. */
 int lattice_map_steps_batch(lattice *const *hs, int32_t count, uint64_t first_map, uint32_t n_maps,
-                            void *hip_stream);
+                            int32_t partner, void *hip_stream);
 
 /* Release the handle (host memory only; caller buffers are untouched). */
 int lattice_destroy(lattice *h);

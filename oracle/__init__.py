@@ -75,7 +75,13 @@ def _configure(L: ctypes.CDLL) -> ctypes.CDLL:
     L.orc_map_build.restype = i64
     L.orc_map_steps.argtypes = [i32, d, d, d, d, u64, u64, u64, i8p, i64p]
     L.orc_map_steps.restype = ctypes.c_int
-    L.orc_map_series.argtypes = [i32, d, d, d, d, u64, u64, u64, u64, i8p, i64p, i64p]
+    L.orc_map_steps_mode.argtypes = [i32, d, d, d, d, u64, ctypes.c_int, u64, u64, i8p, i64p]
+    L.orc_map_steps_mode.restype = ctypes.c_int
+    L.orc_nn_map_pairs.argtypes = [i32]
+    L.orc_nn_map_pairs.restype = i64
+    L.orc_nn_map_build.argtypes = [i32, u64, u64, i64p]
+    L.orc_nn_map_build.restype = i64
+    L.orc_map_series.argtypes = [i32, d, d, d, d, u64, ctypes.c_int, u64, u64, u64, i8p, i64p, i64p]
     L.orc_map_series.restype = ctypes.c_int
     return L
 
@@ -226,36 +232,37 @@ def general_series(L, Delta, V, J, T, seed, codes, every, n_obs, start_step=0):
     return out, track
 
 
-def map_pairs(L: int) -> int:
-    """Pairs per map: max(1, N // 10) (section 3.2)."""
-    return int(lib().orc_map_pairs(L))
+def map_pairs(L: int, nn: bool = False) -> int:
+    """Pairs per map: max(1, N // 10) (section 3.2), or max(1, N // 20) for nearest-neighbour maps."""
+    return int(lib().orc_nn_map_pairs(L) if nn else lib().orc_map_pairs(L))
 
 
-def map_build(L: int, seed: int, m: int):
-    """Map m of the map mode: an (n_pairs, 2) array of site indices and the
-    number of draws the construction consumed."""
-    pairs = np.zeros((map_pairs(L), 2), dtype=np.int64)
-    k = lib().orc_map_build(L, seed, m, _p(pairs, ctypes.c_int64))
+def map_build(L: int, seed: int, m: int, nn: bool = False):
+    """Map m of the map mode (nn: nearest-neighbour partners): an (n_pairs, 2)
+    array of site indices and the number of draws the construction consumed."""
+    pairs = np.zeros((map_pairs(L, nn), 2), dtype=np.int64)
+    build = lib().orc_nn_map_build if nn else lib().orc_map_build
+    k = build(L, seed, m, _p(pairs, ctypes.c_int64))
     if k < 0:
-        raise ValueError("orc_map_build failed")
+        raise ValueError("map build failed")
     return pairs, int(k)
 
 
-def map_steps(L, Delta, V, J, T, seed, codes, n_maps, start_map=0, track=None):
+def map_steps(L, Delta, V, J, T, seed, codes, n_maps, start_map=0, track=None, nn=False):
     """Apply maps start_map .. start_map+n_maps-1 (section 3.2) to codes in place."""
     track = np.zeros(3, dtype=np.int64) if track is None else track
-    rc = lib().orc_map_steps(L, Delta, V, J, T, seed, start_map, n_maps, _p(codes, ctypes.c_int8),
-                             _p(track, ctypes.c_int64))
+    rc = lib().orc_map_steps_mode(L, Delta, V, J, T, seed, int(nn), start_map, n_maps, _p(codes, ctypes.c_int8),
+                                  _p(track, ctypes.c_int64))
     if rc != 0:
         raise ValueError("orc_map_steps failed")
     return track
 
 
-def map_series(L, Delta, V, J, T, seed, codes, every, n_obs, start_map=0):
+def map_series(L, Delta, V, J, T, seed, codes, every, n_obs, start_map=0, nn=False):
     """Map-mode observation series (one row every `every` maps); codes updated in place."""
     track = np.zeros(3, dtype=np.int64)
     out = np.zeros((n_obs, 7), dtype=np.int64)
-    rc = lib().orc_map_series(L, Delta, V, J, T, seed, start_map, every, n_obs,
+    rc = lib().orc_map_series(L, Delta, V, J, T, seed, int(nn), start_map, every, n_obs,
                               _p(codes, ctypes.c_int8), _p(track, ctypes.c_int64), _p(out, ctypes.c_int64))
     if rc != 0:
         raise ValueError("orc_map_series failed")

@@ -476,20 +476,74 @@ int64_t orc_map_build(int32_t L, uint64_t seed, uint64_t m, int64_t *pairs)
     return (int64_t)k;
 }
 
+/* Nearest-neighbour maps: the pairing of the paper's first version (section
+ * 3.2), where the partner is a neighbour of the first site.  Pairs per map:
+ * max(1, floor(N/20)).  Draws come from the same stream as orc_map_build:
+ * a draw gives a = mulhi(w, N); if a is marked the next draw starts over;
+ * otherwise the next draw gives the neighbour index d = w >> 30 (order: x+1,
+ * x-1, y+1, y-1) and b = neighbour d of a; if b is marked the pair is
+ * dropped and the next draw starts over; otherwise a, b and the neighbours
+ * of both are marked and (a, b) is recorded.  Every pair marks at most 8
+ * sites, so fewer than half the sites are ever marked, which leaves an
+ * unmarked neighbour pair for every draw of the map to find. */
+int64_t orc_nn_map_pairs(int32_t L)
+{
+    int64_t n = (int64_t)L * L / 20;
+    return n < 1 ? 1 : n;
+}
+
+int64_t orc_nn_map_build(int32_t L, uint64_t seed, uint64_t m, int64_t *pairs)
+{
+    if (L < 3) return -1;
+    const int64_t N = (int64_t)L * L, n_pairs = orc_nn_map_pairs(L);
+    uint8_t *marked = (uint8_t *)calloc((size_t)N, 1);
+    if (!marked) return -1;
+    uint64_t k = 0;
+    uint32_t w[4] = {0, 0, 0, 0};
+    int64_t count = 0;
+    while (count < n_pairs) {
+        if ((k & 3u) == 0)
+            philox_seeded(seed, (uint32_t)m, DOM_MAP, (uint32_t)(k >> 2), (uint32_t)(m >> 32), w);
+        const int64_t a = (int64_t)mulhi32(w[k & 3u], (uint32_t)N);
+        ++k;
+        if (marked[a]) continue;
+        if ((k & 3u) == 0)
+            philox_seeded(seed, (uint32_t)m, DOM_MAP, (uint32_t)(k >> 2), (uint32_t)(m >> 32), w);
+        const uint32_t d = w[k & 3u] >> 30;
+        ++k;
+        int64_t nb[4];
+        neighbours(L, a, nb);
+        const int64_t b = nb[d];
+        if (marked[b]) continue;
+        pairs[2 * count] = a;
+        pairs[2 * count + 1] = b;
+        ++count;
+        marked[a] = 1;
+        marked[b] = 1;
+        for (int h = 0; h < 2; ++h) {
+            int64_t q[4];
+            neighbours(L, h ? b : a, q);
+            for (int e = 0; e < 4; ++e) marked[q[e]] = 1;
+        }
+    }
+    free(marked);
+    return (int64_t)k;
+}
+
 /* Map steps start_map .. start_map + n_maps - 1: build each map, then apply
  * one coupled-pair Metropolis step to each of its pairs in map order.  Pair i
  * of map m uses Philox counter (m_lo, DOM_MAPSTEP, floor(i/2), m_hi): words
  * h and h+1 with h = 2*(i mod 2) are the configuration and acceptance draws.
  * The pairs of a map do not interact, so any order gives the same result. */
-int orc_map_steps(int32_t L, double Delta, double V, double J, double T, uint64_t seed,
-                  uint64_t start_map, uint64_t n_maps, int8_t *codes, int64_t track[3])
+int orc_map_steps_mode(int32_t L, double Delta, double V, double J, double T, uint64_t seed, int nn,
+                       uint64_t start_map, uint64_t n_maps, int8_t *codes, int64_t track[3])
 {
     if (L < 3) return -1;
-    const int64_t n_pairs = orc_map_pairs(L);
+    const int64_t n_pairs = nn ? orc_nn_map_pairs(L) : orc_map_pairs(L);
     int64_t *pairs = (int64_t *)malloc((size_t)(2 * n_pairs) * sizeof(int64_t));
     if (!pairs) return -1;
     for (uint64_t m = start_map; m < start_map + n_maps; ++m) {
-        if (orc_map_build(L, seed, m, pairs) < 0) {
+        if ((nn ? orc_nn_map_build(L, seed, m, pairs) : orc_map_build(L, seed, m, pairs)) < 0) {
             free(pairs);
             return -1;
         }
@@ -504,13 +558,20 @@ int orc_map_steps(int32_t L, double Delta, double V, double J, double T, uint64_
     return 0;
 }
 
-/* Same for the map mode; one observation every `every` maps. */
-int orc_map_series(int32_t L, double Delta, double V, double J, double T, uint64_t seed,
+int orc_map_steps(int32_t L, double Delta, double V, double J, double T, uint64_t seed,
+                  uint64_t start_map, uint64_t n_maps, int8_t *codes, int64_t track[3])
+{
+    return orc_map_steps_mode(L, Delta, V, J, T, seed, 0, start_map, n_maps, codes, track);
+}
+
+/* Same for the map mode (nn = 1: nearest-neighbour maps); one observation
+ * every `every` maps. */
+int orc_map_series(int32_t L, double Delta, double V, double J, double T, uint64_t seed, int nn,
                    uint64_t start_map, uint64_t every, uint64_t n_obs, int8_t *codes,
                    int64_t track[3], int64_t *series)
 {
     for (uint64_t k = 0; k < n_obs; ++k) {
-        int rc = orc_map_steps(L, Delta, V, J, T, seed, start_map + k * every, every, codes, track);
+        int rc = orc_map_steps_mode(L, Delta, V, J, T, seed, nn, start_map + k * every, every, codes, track);
         if (rc) return rc;
         orc_observables(L, codes, &series[7 * k]);
     }

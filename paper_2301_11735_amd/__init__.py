@@ -45,6 +45,7 @@ EXPORTS = (
     "lat_server_destroy",
 )
 REQ_QUEUED, REQ_RESIDENT, REQ_FINISHED = 0, 1, 2
+MAP_ANY, MAP_NEIGHBOUR = 0, 1
 
 
 class LatParams(ctypes.Structure):
@@ -155,9 +156,10 @@ def lib() -> ctypes.CDLL:
         L.lattice_batch_graph_read.restype = ctypes.c_int
         L.lattice_batch_graph_destroy.argtypes = [vp]
         L.lattice_batch_graph_destroy.restype = ctypes.c_int
-        L.lattice_map_steps.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint32]
+        L.lattice_map_steps.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32]
         L.lattice_map_steps.restype = ctypes.c_int
-        L.lattice_map_steps_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32, vp]
+        L.lattice_map_steps_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32,
+                                              ctypes.c_int32, vp]
         L.lattice_map_steps_batch.restype = ctypes.c_int
         L.lattice_destroy.argtypes = [vp]
         L.lattice_destroy.restype = ctypes.c_int
@@ -252,9 +254,9 @@ class Lattice:
     def sweep(self, sweeps: int = 1):
         _check(lib().lattice_sweep(self.handle, sweeps))
 
-    def map_steps(self, first_map: int, n_maps: int = 1):
-        """Apply maps first_map .. first_map+n_maps-1 of the map mode."""
-        _check(lib().lattice_map_steps(self.handle, first_map, n_maps))
+    def map_steps(self, first_map: int, n_maps: int = 1, partner: int = 0):
+        """Apply maps first_map .. first_map+n_maps-1 of the map mode (partner MAP_ANY or MAP_NEIGHBOUR)."""
+        _check(lib().lattice_map_steps(self.handle, first_map, n_maps, partner))
 
     def observables(self) -> LatObs:
         o = LatObs()
@@ -282,9 +284,10 @@ def _handles(lattices):
     return (ctypes.c_void_p * len(lattices))(*[lat.handle.value for lat in lattices])
 
 
-def map_steps_batch(lattices, first_map: int, n_maps: int, stream=None):
-    """Apply maps first_map .. first_map+n_maps-1 (map mode) to several lattices in one call."""
-    _check(lib().lattice_map_steps_batch(_handles(lattices), len(lattices), first_map, n_maps,
+def map_steps_batch(lattices, first_map: int, n_maps: int, partner: int = 0, stream=None):
+    """Apply maps first_map .. first_map+n_maps-1 (map mode; partner MAP_ANY or
+    MAP_NEIGHBOUR) to several lattices in one call."""
+    _check(lib().lattice_map_steps_batch(_handles(lattices), len(lattices), first_map, n_maps, partner,
                                          _stream_handle(stream)))
 
 

@@ -119,6 +119,7 @@ struct MapArgs {
     int count;
     uint8_t *scratch[kMaxBatch];
     uint32_t first_map_lo, first_map_hi, n_maps;
+    int32_t nn;  // 1: nearest-neighbour partners, max(1, N/20) pairs per map
 };
 // LDS bytes one block needs for a lattice of side L.
 inline size_t map_lds_bytes(int L)

@@ -15,7 +15,8 @@ using namespace lat::detail;
 
 namespace {
 
-int enqueue_map_steps(lattice *const *hs, int32_t count, uint64_t first_map, uint32_t n_maps, hipStream_t stream)
+int enqueue_map_steps(lattice *const *hs, int32_t count, uint64_t first_map, uint32_t n_maps, int32_t partner,
+                      hipStream_t stream)
 {
     for (int32_t b = 0; b < count; b += kMaxBatch) {
         MapArgs a{};
@@ -23,6 +24,7 @@ int enqueue_map_steps(lattice *const *hs, int32_t count, uint64_t first_map, uin
         a.first_map_lo = (uint32_t)first_map;
         a.first_map_hi = (uint32_t)(first_map >> 32);
         a.n_maps = n_maps;
+        a.nn = partner;
         int max_L = 0;
         for (int i = 0; i < a.count; ++i) {
             a.scratch[i] = hs[b + i]->d_scratch;
@@ -52,22 +54,25 @@ int check_batch(lattice *const *hs, int32_t count)
 
 extern "C" {
 
-int lattice_map_steps(lattice *h, uint64_t first_map, uint32_t n_maps)
+int lattice_map_steps(lattice *h, uint64_t first_map, uint32_t n_maps, int32_t partner)
 {
     if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
+    if (partner != LAT_MAP_ANY && partner != LAT_MAP_NEIGHBOUR) return fail(LAT_EINVAL, "unknown partner rule");
     lattice *one[1] = {h};
     const int rc = check_batch(one, 1);
     if (rc) return rc;
     if (n_maps == 0) return LAT_OK;
-    return enqueue_map_steps(one, 1, first_map, n_maps, h->stream);
+    return enqueue_map_steps(one, 1, first_map, n_maps, partner, h->stream);
 }
 
-int lattice_map_steps_batch(lattice *const *hs, int32_t count, uint64_t first_map, uint32_t n_maps, void *hip_stream)
+int lattice_map_steps_batch(lattice *const *hs, int32_t count, uint64_t first_map, uint32_t n_maps, int32_t partner,
+                            void *hip_stream)
 {
+    if (partner != LAT_MAP_ANY && partner != LAT_MAP_NEIGHBOUR) return fail(LAT_EINVAL, "unknown partner rule");
     const int rc = check_batch(hs, count);
     if (rc) return rc;
     if (n_maps == 0 || count == 0) return LAT_OK;
-    return enqueue_map_steps(hs, count, first_map, n_maps, (hipStream_t)hip_stream);
+    return enqueue_map_steps(hs, count, first_map, n_maps, partner, (hipStream_t)hip_stream);
 }
 
 }  // extern "C"

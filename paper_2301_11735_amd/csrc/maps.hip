@@ -52,6 +52,7 @@ __device__ __forceinline__ void mark(uint32_t *bitmap, uint32_t s) { bitmap[s >>
 // at the start of the round is rejected without touching LDS, any other is
 // checked against the live bitmap (a broadcast LDS read, which the in-order LDS
 // queue orders after the marks already issued).  Marks are LDS atomic ors.
+template <bool NN>
 __device__ void build_map(uint32_t *bitmap, uint32_t *pairs, int L, uint32_t N, uint32_t n_pairs, uint32_t m_lo,
                           uint32_t m_hi, uint32_t key0, uint32_t key1)
 {
@@ -61,6 +62,7 @@ __device__ void build_map(uint32_t *bitmap, uint32_t *pairs, int L, uint32_t N, 
     while (count < n_pairs) {
         // draws k .. k+255: draw d is word d mod 4 of Philox call d / 4, held by lane d / 4
         const u32x4 w = philox4x32_10(m_lo, kDomMap, (k >> 2) + lane, m_hi, key0, key1);
+        const uint32_t raw[4] = {w.x, w.y, w.z, w.w};
         const uint32_t c[4] = {mulhi_u32(w.x, N), mulhi_u32(w.y, N), mulhi_u32(w.z, N), mulhi_u32(w.w, N)};
         uint32_t nbv[4][4];
         uint64_t pre[4];
@@ -72,10 +74,41 @@ __device__ void build_map(uint32_t *bitmap, uint32_t *pairs, int L, uint32_t N, 
         for (int l = 0; l < 64 && count < n_pairs; ++l) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                if (count >= n_pairs || ((pre[q] >> l) & 1u)) continue;
+                if (count >= n_pairs) continue;
+                if (NN && need_b) {
+                    // nearest-neighbour partner: this draw picks neighbour raw >> 30 of a
+                    need_b = 0;
+                    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)raw[q], l) >> 30;
+                    const uint32_t b = d == 0 ? an[0] : d == 1 ? an[1] : d == 2 ? an[2] : an[3];
+                    const uint32_t bw = (uint32_t)__builtin_amdgcn_readfirstlane((int)bitmap[b >> 5]);
+                    if (bw & (1u << (b & 31u))) continue;  // drop the pair, start over
+                    uint32_t bn[4];
+                    site_neighbours(L, b, bn);
+                    if (lane == 0) {
+                        pairs[count] = a_site | (b << 16);
+                        atomicOr(&bitmap[a_site >> 5], 1u << (a_site & 31u));
+                        atomicOr(&bitmap[b >> 5], 1u << (b & 31u));
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            atomicOr(&bitmap[an[e] >> 5], 1u << (an[e] & 31u));
+                            atomicOr(&bitmap[bn[e] >> 5], 1u << (bn[e] & 31u));
+                        }
+                    }
+                    ++count;
+                    continue;
+                }
+                if ((pre[q] >> l) & 1u) continue;
                 const uint32_t site = (uint32_t)__builtin_amdgcn_readlane((int)c[q], l);
                 const uint32_t word = (uint32_t)__builtin_amdgcn_readfirstlane((int)bitmap[site >> 5]);
                 if (word & (1u << (site & 31u))) continue;
+                if (NN) {
+                    // first site of a nearest-neighbour pair: marked only once the pair is kept
+                    a_site = site;
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) an[d] = (uint32_t)__builtin_amdgcn_readlane((int)nbv[q][d], l);
+                    need_b = 1;
+                    continue;
+                }
                 if (lane == 0) atomicOr(&bitmap[site >> 5], 1u << (site & 31u));
                 if (!need_b) {
                     a_site = site;
@@ -159,7 +192,8 @@ __global__ void __launch_bounds__(kMapThreads) k_map_steps(MapArgs args)
     const LatDesc d = *(const LatDesc *)(scr + kScrDesc);
     const int L = d.L;
     const uint32_t N = (uint32_t)L * (uint32_t)L;
-    const uint32_t n_pairs = N / 10u < 1u ? 1u : N / 10u;
+    const uint32_t per = args.nn ? 20u : 10u;
+    const uint32_t n_pairs = N / per < 1u ? 1u : N / per;
     uint32_t *thr = smem;                                   // kTabSize
     uint8_t *codes = (uint8_t *)(smem + kTabSize);          // N bytes
     uint32_t *bitmap = smem + kTabSize + (N + 3u) / 4u;     // ceil(N/32) words
@@ -189,7 +223,12 @@ __global__ void __launch_bounds__(kMapThreads) k_map_steps(MapArgs args)
         const uint32_t m_lo = (uint32_t)m, m_hi = (uint32_t)(m >> 32);
         for (uint32_t i = threadIdx.x; i < (N + 31u) / 32u; i += blockDim.x) bitmap[i] = 0u;
         __syncthreads();
-        if (threadIdx.x < 64) build_map(bitmap, pairs, L, N, n_pairs, m_lo, m_hi, d.key0, d.key1);
+        if (threadIdx.x < 64) {
+            if (args.nn)
+                build_map<true>(bitmap, pairs, L, N, n_pairs, m_lo, m_hi, d.key0, d.key1);
+            else
+                build_map<false>(bitmap, pairs, L, N, n_pairs, m_lo, m_hi, d.key0, d.key1);
+        }
         __syncthreads();
         // pairs 2c and 2c+1 share Philox call c
         for (uint32_t c = threadIdx.x; 2u * c < n_pairs; c += blockDim.x) {

@@ -116,8 +116,9 @@ def test_batch_graph_rejects_bad_arguments_without_a_device():
 
 def test_map_calls_on_null_handles_fail_cleanly():
     L = lat.lib()
-    assert L.lattice_map_steps(None, 0, 1) == lat.LAT_ESTATE
-    assert L.lattice_map_steps_batch(None, 1, 0, 1, None) == lat.LAT_EINVAL
-    assert L.lattice_map_steps_batch(None, 0, 0, 1, None) == lat.LAT_OK
+    assert L.lattice_map_steps(None, 0, 1, 0) == lat.LAT_ESTATE
+    assert L.lattice_map_steps_batch(None, 1, 0, 1, 0, None) == lat.LAT_EINVAL
+    assert L.lattice_map_steps_batch(None, 0, 0, 1, 0, None) == lat.LAT_OK
+    assert L.lattice_map_steps_batch(None, 0, 0, 1, 7, None) == lat.LAT_EINVAL
     fake = (ctypes.c_void_p * 1)(None)
-    assert L.lattice_map_steps_batch(fake, 1, 0, 1, None) == lat.LAT_ESTATE
+    assert L.lattice_map_steps_batch(fake, 1, 0, 1, 1, None) == lat.LAT_ESTATE

@@ -31,9 +31,9 @@ def _oracle(spec):
                                 n_charged=spec.n_charged)
 
 
-def _oracle_maps(spec, o, first, n):
+def _oracle_maps(spec, o, first, n, nn=False):
     oracle.map_steps(spec.L, spec.Delta, spec.V, spec.J, spec.T, spec.seed, o.codes, n, start_map=first,
-                     track=o.track)
+                     track=o.track, nn=nn)
 
 
 def _assert_same(g, o, where):
@@ -56,13 +56,14 @@ def _assert_same(g, o, where):
     SMALL.with_(L=64, encoding=1, n=0.3, T=0.5, seed=21),
     SMALL.with_(L=192, encoding=1, Delta=0.9, V=-0.8, T=2.2, seed=22),
 ], ids=lambda s: f"{'2bit' if s.encoding else 'int8'}-L{s.L}")
-def test_map_steps_match_oracle(spec):
-    _say(f"case maps L={spec.L} enc={spec.encoding} seed={spec.seed}")
+@pytest.mark.parametrize("partner", [lat.MAP_ANY, lat.MAP_NEIGHBOUR], ids=["any", "neighbour"])
+def test_map_steps_match_oracle(spec, partner):
+    _say(f"case maps L={spec.L} enc={spec.encoding} seed={spec.seed} partner={partner}")
     g, o = _make(spec), _oracle(spec)
     done = 0
     for k in (1, 2, 5, 12):
-        g.map_steps(done, k)
-        _oracle_maps(spec, o, done, k)
+        g.map_steps(done, k, partner)
+        _oracle_maps(spec, o, done, k, nn=partner == lat.MAP_NEIGHBOUR)
         done += k
         _assert_same(g, o, f"after {done} maps")
     g.destroy()
@@ -98,11 +99,14 @@ def test_map_batch_equals_oracle_and_alone():
     gs = [_make(s) for s in specs]
     os_ = [_oracle(s) for s in specs]
     lat.map_steps_batch(gs, 7, 6)
+    lat.map_steps_batch(gs, 13, 4, lat.MAP_NEIGHBOUR)
     for s, g, o in zip(specs, gs, os_):
         _oracle_maps(s, o, 7, 6)
+        _oracle_maps(s, o, 13, 4, nn=True)
         _assert_same(g, o, f"batch L={s.L}")
     alone = _make(specs[4])
     alone.map_steps(7, 6)
+    alone.map_steps(13, 4, lat.MAP_NEIGHBOUR)
     assert np.array_equal(alone.read_state(), gs[4].read_state())
 
 
@@ -111,3 +115,35 @@ def test_map_mode_rejects_large_lattices():
     with pytest.raises(lat.LatticeError):
         g.map_steps(0, 1)
     g.destroy()
+
+
+def test_neighbour_pairs_lose_the_low_temperature_fluctuations():
+    """The paper's first pairing (partners restricted to nearest neighbours)
+    freezes on 4x4 at low temperature: every replica stays in one
+    configuration and the heat capacity collapses, while random partners give
+    the exact energy and heat capacity.  64 replicas each, V = 2, Q = 4,
+    T = 0.3; C per replica from its own series, then averaged."""
+    from tests import exact
+
+    _say("case neighbour pairs vs random pairs on 4x4")
+    L, N, Q, T = 4, 16, 4, 0.3
+    Delta, V, J = 0.25, 2.0, 1.0
+    ex = exact.sector_averages(L, Q, Delta, V, J, T)
+    res = {}
+    for partner in (lat.MAP_ANY, lat.MAP_NEIGHBOUR):
+        gs = [lat.Lattice(L, 0.25, Delta, V, J, T, 2000 + r, n_charged=4) for r in range(64)]
+        obs = lat.BatchObservables(len(gs))
+        lat.map_steps_batch(gs, 0, 2000, partner)
+        E = []
+        for k in range(2000):
+            lat.map_steps_batch(gs, 2000 + 10 * k, 10, partner)
+            E.append([o.E for o in obs(gs)])
+        E = np.asarray(E)
+        e_rep, c_rep = E.mean(axis=0), E.var(axis=0) / (N * T * T)
+        n = e_rep.size
+        res[partner] = (e_rep.mean(), e_rep.std(ddof=1) / np.sqrt(n), c_rep.mean(), c_rep.std(ddof=1) / np.sqrt(n))
+    e, e_err, c, c_err = res[lat.MAP_ANY]
+    assert abs(e - ex["E"]) < 4 * e_err + 0.01 * abs(ex["E"]), (e, e_err, ex["E"])
+    assert abs(c - ex["C"]) < 4 * c_err + 0.05 * ex["C"], (c, c_err, ex["C"])
+    c_nn = res[lat.MAP_NEIGHBOUR][2]
+    assert c_nn < 0.25 * ex["C"], (c_nn, ex["C"])

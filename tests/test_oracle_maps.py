@@ -106,3 +106,67 @@ def test_map_mode_infinite_delta_reduces_to_onsager(T):
     assert np.all(ser[:, 1] == 0)
     u = 0.25 * J * ser[:, 3] / (L * L)
     _check("u", *block_mean(u, n_blocks=25), onsager_energy_per_site(T, 0.25 * J))
+
+
+# ---------------------------------------------------------------- nearest-neighbour maps
+@pytest.mark.parametrize("L", [3, 4, 5, 8, 10, 16, 33])
+def test_nn_map_pairs_are_adjacent_and_never_interact(L):
+    N = L * L
+    for m in (0, 3):
+        pairs, draws = oracle.map_build(L, 13, m, nn=True)
+        assert len(pairs) == max(1, N // 20)
+        sites = pairs.reshape(-1).tolist()
+        assert len(set(sites)) == len(sites)
+        cover = [{a, b} | _neighbours(L, a) | _neighbours(L, b) for a, b in pairs.tolist()]
+        for j, (a, b) in enumerate(pairs.tolist()):
+            assert b in _neighbours(L, a), f"pair {j} of map {m} is not a neighbour pair"
+            for i in range(j):
+                assert a not in cover[i] and b not in cover[i]
+
+
+def test_nn_map_first_site_and_direction_uniform():
+    L, N, n = 4, 16, 6000
+    first = np.zeros(N, dtype=np.int64)
+    direction = np.zeros(4, dtype=np.int64)
+    for m in range(n):
+        (a, b), = oracle.map_build(L, 5, m, nn=True)[0].tolist()
+        first[a] += 1
+        x, y = a % L, a // L
+        direction[[y * L + (x + 1) % L, y * L + (x - 1) % L, ((y + 1) % L) * L + x, ((y - 1) % L) * L + x].index(b)] += 1
+    assert float(((first - n / N) ** 2 / (n / N)).sum()) < 50.0
+    assert float(((direction - n / 4) ** 2 / (n / 4)).sum()) < 25.0
+
+
+def _series_energy(L, Delta, V, J, T, Q, nn, seed, n_obs):
+    N = L * L
+    codes = np.zeros(N, dtype=np.int8)
+    codes[:Q] = 2
+    ser, _ = oracle.map_series(L, Delta, V, J, T, seed=seed, codes=codes, every=2, n_obs=n_obs, nn=nn)
+    ser = ser[10000:]
+    return _energies(ser, Delta, V, J)
+
+
+def test_nn_maps_match_exact_where_they_mix():
+    # weak charge repulsion: nearest-neighbour pairs still sample the sector
+    L, N, Q, T = 4, 16, 2, 1.0
+    Delta, V, J = 0.25, 0.5, 1.0
+    E = _series_energy(L, Delta, V, J, T, Q, True, 5, 150000)
+    ex = exact.sector_averages(L, Q, Delta, V, J, T)
+    _check("E", *block_mean(E), ex["E"])
+    _check("C", *block_heat_capacity(E, N, T), ex["C"])
+
+
+def test_nn_maps_lose_the_low_temperature_states_random_pairs_reach():
+    """Section 3.2: with partners restricted to nearest neighbours the 4x4
+    low-temperature results miss the exact ones -- the chain freezes and the
+    heat capacity loses its structure -- while long-range random pairs
+    reproduce them.  Strong charge repulsion (V = 2) at T = 0.3, Q = 4."""
+    L, N, Q, T = 4, 16, 4, 0.3
+    Delta, V, J = 0.25, 2.0, 1.0
+    ex = exact.sector_averages(L, Q, Delta, V, J, T)
+    E_rand = _series_energy(L, Delta, V, J, T, Q, False, 5, 100000)
+    _check("E random pairs", *block_mean(E_rand), ex["E"])
+    _check("C random pairs", *block_heat_capacity(E_rand, N, T), ex["C"])
+    E_nn = _series_energy(L, Delta, V, J, T, Q, True, 5, 100000)
+    C_nn, _ = block_heat_capacity(E_nn, N, T)
+    assert C_nn < 0.25 * ex["C"], f"nearest-neighbour pairs kept the fluctuations: C = {C_nn:.4f} vs {ex['C']:.4f}"

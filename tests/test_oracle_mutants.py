@@ -74,6 +74,11 @@ def _pin_map_adjacency():
     maps.test_map_first_site_uniform_and_partner_may_be_adjacent()
 
 
+def _pin_nn_map_structure():
+    for L in (8, 10, 16):
+        maps.test_nn_map_pairs_are_adjacent_and_never_interact(L)
+
+
 def _pin_map_chain():
     maps.test_map_mode_matches_exact_enumeration(4, 2, 1.0)
 
@@ -105,6 +110,9 @@ MUTANTS = [
     ("map: partner drawn only among sites not adjacent to the first", "site[h] = cand;\n                    break;",
      "site[h] = cand;\n                    if (h == 0) { int64_t q[4]; neighbours(L, cand, q); "
      "for (int d = 0; d < 4; ++d) marked[q[d]] = 1; }\n                    break;", _pin_map_adjacency),
+    ("nearest-neighbour map: neighbours of the partner not marked", "neighbours(L, h ? b : a, q);",
+     "neighbours(L, a, q);", _pin_nn_map_structure),
+    ("nearest-neighbour map: partner not checked for a mark", "if (marked[b]) continue;", ";", _pin_nn_map_structure),
     ("map step: a pair's configuration drawn with the acceptance word", "pairs[2 * i + 1], w[h], w[h + 1],",
      "pairs[2 * i + 1], w[h + 1], w[h + 1],", _pin_map_chain),
 ]
