@@ -81,6 +81,9 @@ def _configure(L: ctypes.CDLL) -> ctypes.CDLL:
     L.orc_nn_map_pairs.restype = i64
     L.orc_nn_map_build.argtypes = [i32, u64, u64, i64p]
     L.orc_nn_map_build.restype = i64
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.orc_mu_sweeps.argtypes = [i32, d, d, d, d, u64, u64, u64, d, i64, dp, i8p, i64p, dp, i64p]
+    L.orc_mu_sweeps.restype = ctypes.c_int
     L.orc_map_series.argtypes = [i32, d, d, d, d, u64, ctypes.c_int, u64, u64, u64, i8p, i64p, i64p]
     L.orc_map_series.restype = ctypes.c_int
     return L
@@ -267,3 +270,18 @@ def map_series(L, Delta, V, J, T, seed, codes, every, n_obs, start_map=0, nn=Fal
     if rc != 0:
         raise ValueError("orc_map_series failed")
     return out, track
+
+
+def mu_sweeps(L, Delta, V, J, T, seed, codes, n_sweeps, kappa, Q, mu, start_sweep=0, track=None):
+    """Penalty-mode sweeps (section 2.2, reading R15) on codes in place.  Returns
+    (final mu, mu used in each sweep, sum S after each sweep, track)."""
+    track = np.zeros(3, dtype=np.int64) if track is None else track
+    mu_c = ctypes.c_double(mu)
+    mus = np.zeros(n_sweeps, dtype=np.float64)
+    sums = np.zeros(n_sweeps, dtype=np.int64)
+    rc = lib().orc_mu_sweeps(L, Delta, V, J, T, seed, start_sweep, n_sweeps, kappa, Q, ctypes.byref(mu_c),
+                             _p(codes, ctypes.c_int8), _p(track, ctypes.c_int64), _p(mus, ctypes.c_double),
+                             _p(sums, ctypes.c_int64))
+    if rc != 0:
+        raise ValueError("orc_mu_sweeps failed")
+    return mu_c.value, mus, sums, track

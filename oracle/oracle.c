@@ -31,6 +31,9 @@
  *       paper's random maps (section 3.2);
  *   R6  randomness is Philox4x32-10 keyed by the seed, with the counter
  *       naming the sweep, the phase and the pair.
+ *   R15 penalty mode (section 2.2, the prior method): single-site
+ *       checkerboard Metropolis on E - mu sum S, each site proposing one of
+ *       its 4 codes, mu adjusted after every sweep by mu += kappa (Q - sum S)/N.
  *   R12 map mode (section 3.2 as printed): maps of max(1, floor(N/10))
  *       pairs built by the paper's sequential algorithm, the site draws
  *       taken from Philox words in counter order; a pair's two sites may be
@@ -83,6 +86,7 @@ static void philox_seeded(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
 #define DOM_GENERAL  0x300u
 #define DOM_MAP      0x400u
 #define DOM_MAPSTEP  0x500u
+#define DOM_MU       0x600u
 
 static uint32_t mulhi32(uint32_t a, uint32_t b)
 {
@@ -574,6 +578,83 @@ int orc_map_series(int32_t L, double Delta, double V, double J, double T, uint64
         int rc = orc_map_steps_mode(L, Delta, V, J, T, seed, nn, start_map + k * every, every, codes, track);
         if (rc) return rc;
         orc_observables(L, codes, &series[7 * k]);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Penalty mode (section 2.2): the method the paper sets out to replace.  The
+ * energy gets the term -mu sum_i S_i, sites are updated one at a time by the
+ * classical Metropolis rule (no pairs, so the charge is free to change), and
+ * mu is adjusted automatically to steer sum S towards Q.
+ *   - a sweep is two half-sweeps over the checkerboard colours c = (x+y) mod 2,
+ *     c = 0 first; site (x, y) of colour c has index k = y*(L/2) + floor(x/2);
+ *   - site k of colour c in sweep s uses Philox counter (s_lo, 0x600 + c,
+ *     floor(k/2), s_hi), words h, h+1 with h = 2*(k mod 2): the new code is
+ *     word h >> 30 (one of the 4 codes, the current one included), word h+1
+ *     is the acceptance draw;
+ *   - dE = Delta nD + V nV + (J/4) nJ - mu dS with the site's changes of S^2,
+ *     S * (sum of neighbour S), sigma * (sum of neighbour sigma) and S; the
+ *     threshold follows orc_threshold's convention;
+ *   - after the sweep, with sum S of the new configuration:
+ *     mu = mu + kappa * (Q - sum S) / N (a proportional controller; the paper
+ *     says only that mu is adjusted automatically).
+ * mu_series[i] / sumS_series[i] (if not null) receive the mu used in sweep
+ * start+i and the sum S after it.  track[] accumulates the accepted (nD, nV,
+ * nJ) of the physical energy (the penalty term excluded). */
+static uint32_t mu_threshold(double Delta, double V, double J, double T, double mu, int nD, int nV, int nJ, int dS)
+{
+    double dE = Delta * nD + V * nV + 0.25 * J * nJ - mu * dS;
+    if (dE <= 0.0) return 0xFFFFFFFFu;
+    double x = exp(-dE / T) * 4294967296.0;
+    double f = floor(x);
+    if (f >= 4294967294.0) return 0xFFFFFFFEu;
+    return (uint32_t)f;
+}
+
+int orc_mu_sweeps(int32_t L, double Delta, double V, double J, double T, uint64_t seed, uint64_t start_sweep,
+                  uint64_t n_sweeps, double kappa, int64_t Q, double *mu, int8_t *codes, int64_t track[3],
+                  double *mu_series, int64_t *sumS_series)
+{
+    if (L < 4 || L % 2 != 0) return -1;
+    const int64_t N = (int64_t)L * L, half = L / 2;
+    for (uint64_t s = start_sweep; s < start_sweep + n_sweeps; ++s) {
+        for (int c = 0; c < 2; ++c) {
+            for (int64_t y = 0; y < L; ++y) {
+                for (int64_t xh = 0; xh < half; ++xh) {
+                    const int64_t x = 2 * xh + ((y + c) & 1);
+                    const int64_t k = y * half + xh;
+                    uint32_t w[4];
+                    philox_seeded(seed, (uint32_t)s, DOM_MU + (uint32_t)c, (uint32_t)(k >> 1), (uint32_t)(s >> 32), w);
+                    const int h = 2 * (int)(k & 1);
+                    const int64_t i = y * L + x;
+                    const int c0 = codes[i], c1 = (int)(w[h] >> 30);
+                    int64_t nb[4];
+                    neighbours(L, i, nb);
+                    int sS = 0, sG = 0;
+                    for (int d = 0; d < 4; ++d) {
+                        sS += S_OF[codes[nb[d]]];
+                        sG += SIG_OF[codes[nb[d]]];
+                    }
+                    const int dS = S_OF[c1] - S_OF[c0];
+                    const int nD = S_OF[c1] * S_OF[c1] - S_OF[c0] * S_OF[c0];
+                    const int nV = dS * sS;
+                    const int nJ = (SIG_OF[c1] - SIG_OF[c0]) * sG;
+                    const uint32_t thr = mu_threshold(Delta, V, J, T, *mu, nD, nV, nJ, dS);
+                    if (thr == 0xFFFFFFFFu || w[h + 1] < thr) {
+                        codes[i] = (int8_t)c1;
+                        track[0] += nD;
+                        track[1] += nV;
+                        track[2] += nJ;
+                    }
+                }
+            }
+        }
+        int64_t sumS = 0;
+        for (int64_t i = 0; i < N; ++i) sumS += S_OF[codes[i]];
+        if (mu_series) mu_series[s - start_sweep] = *mu;
+        if (sumS_series) sumS_series[s - start_sweep] = sumS;
+        *mu = *mu + kappa * (double)(Q - sumS) / (double)N;
     }
     return 0;
 }

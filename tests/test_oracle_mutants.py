@@ -16,6 +16,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_maps as maps
+from tests import test_oracle_mu as mu_pins
 from tests import test_oracle_model as model
 from tests import test_oracle_stats as stats
 
@@ -79,6 +80,14 @@ def _pin_nn_map_structure():
         maps.test_nn_map_pairs_are_adjacent_and_never_interact(L)
 
 
+def _pin_grand_canonical():
+    mu_pins.test_fixed_mu_samples_the_grand_canonical_ensemble(0.3, 1.0)
+
+
+def _pin_controller():
+    mu_pins.test_controller_holds_the_charge_on_average()
+
+
 def _pin_map_chain():
     maps.test_map_mode_matches_exact_enumeration(4, 2, 1.0)
 
@@ -113,6 +122,10 @@ MUTANTS = [
     ("nearest-neighbour map: neighbours of the partner not marked", "neighbours(L, h ? b : a, q);",
      "neighbours(L, a, q);", _pin_nn_map_structure),
     ("nearest-neighbour map: partner not checked for a mark", "if (marked[b]) continue;", ";", _pin_nn_map_structure),
+    ("penalty term sign flipped", "0.25 * J * nJ - mu * dS;", "0.25 * J * nJ + mu * dS;", _pin_grand_canonical),
+    ("penalty controller pushes the wrong way", "*mu = *mu + kappa * (double)(Q - sumS) / (double)N;",
+     "*mu = *mu + kappa * (double)(sumS - Q) / (double)N;", _pin_controller),
+    ("penalty mode: neighbour spins ignored", "sG += SIG_OF[codes[nb[d]]];", ";", _pin_grand_canonical),
     ("map step: a pair's configuration drawn with the acceptance word", "pairs[2 * i + 1], w[h], w[h + 1],",
      "pairs[2 * i + 1], w[h + 1], w[h + 1],", _pin_map_chain),
 ]
