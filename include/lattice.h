@@ -258,6 +258,27 @@ int lattice_map_steps(lattice *h, uint64_t first_map, uint32_t n_maps, int32_t p
 int lattice_map_steps_batch(lattice *const *hs, int32_t count, uint64_t first_map, uint32_t n_maps,
                             int32_t partner, void *hip_stream);
 
+/* Penalty mode (section 2.2): the prior method the paper replaces, kept to
+ * show why.  The energy gets the term -mu * sum_i S_i and sites are updated
+ * one at a time (checkerboard colours c = (x+y) mod 2, c = 0 first), so the
+ * charge is free to change; after every sweep mu is adjusted by the
+ * proportional controller mu += kappa * (Q - sum S) / N (Q: the handle's
+ * target charge; the paper says only that mu is adjusted automatically).
+ * Site k of colour c (row k / (L/2), column 2 (k mod L/2) + ((row + c) & 1))
+ * in sweep s proposes code w >> 30 from word 2(k mod 2) of Philox at counter
+ * (s_lo, 0x600 + c, k / 2, s_hi), the next word being its acceptance draw;
+ * thresholds of dE = Delta nD + V nV + (J/4) nJ - mu dS follow the convention
+ * of the coupled-pair mode.  Runs sweeps first_sweep .. first_sweep +
+ * n_sweeps - 1 and synchronises the handle's stream after each (the
+ * controller needs sum S).  *mu is the starting mu on entry and the next
+ * sweep's mu on return; mu_series / sumS_series (each n_sweeps long, may be
+ * null) receive the mu of every sweep and sum S after it.  The tracker keeps
+ * counting the physical energy (without the penalty term).  Int8 lattices
+ * only.  Errors: LAT_ESTATE, LAT_EINVAL (2-bit lattice, null or non-finite
+ * mu, non-finite kappa), LAT_EHIP. */
+int lattice_mu_sweeps(lattice *h, uint64_t first_sweep, uint32_t n_sweeps, double kappa, double *mu,
+                      double *mu_series, int64_t *sumS_series);
+
 /* Release the handle (host memory only; caller buffers are untouched). */
 int lattice_destroy(lattice *h);
 

@@ -131,14 +131,19 @@ int orc_pair_config(int q, int j, int out[2])
  *   else    -> min(floor(exp(-dE/T) * 2^32), 0xFFFFFFFE).
  * A proposal is accepted iff thr == 0xFFFFFFFF or u < thr for a uniform
  * 32-bit draw u. */
-uint32_t orc_threshold(double Delta, double V, double J, double T, int nD, int nV, int nJ)
+static uint32_t threshold_of_dE(double dE, double T)
 {
-    double dE = Delta * nD + V * nV + 0.25 * J * nJ;
     if (dE <= 0.0) return 0xFFFFFFFFu;
     double x = exp(-dE / T) * 4294967296.0;
     double f = floor(x);
     if (f >= 4294967294.0) return 0xFFFFFFFEu;
     return (uint32_t)f;
+}
+
+uint32_t orc_threshold(double Delta, double V, double J, double T, int nD, int nV, int nJ)
+{
+    double dE = Delta * nD + V * nV + 0.25 * J * nJ;
+    return threshold_of_dE(dE, T);
 }
 
 /* ------------------------------------------------------------------ */
@@ -605,11 +610,7 @@ int orc_map_series(int32_t L, double Delta, double V, double J, double T, uint64
 static uint32_t mu_threshold(double Delta, double V, double J, double T, double mu, int nD, int nV, int nJ, int dS)
 {
     double dE = Delta * nD + V * nV + 0.25 * J * nJ - mu * dS;
-    if (dE <= 0.0) return 0xFFFFFFFFu;
-    double x = exp(-dE / T) * 4294967296.0;
-    double f = floor(x);
-    if (f >= 4294967294.0) return 0xFFFFFFFEu;
-    return (uint32_t)f;
+    return threshold_of_dE(dE, T);
 }
 
 int orc_mu_sweeps(int32_t L, double Delta, double V, double J, double T, uint64_t seed, uint64_t start_sweep,

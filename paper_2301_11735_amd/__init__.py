@@ -34,6 +34,7 @@ EXPORTS = (
     "lattice_batch_graph_destroy",
     "lattice_map_steps",
     "lattice_map_steps_batch",
+    "lattice_mu_sweeps",
     "lattice_destroy",
     "lattice_last_error",
     "lat_server_create",
@@ -161,6 +162,10 @@ def lib() -> ctypes.CDLL:
         L.lattice_map_steps_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32,
                                               ctypes.c_int32, vp]
         L.lattice_map_steps_batch.restype = ctypes.c_int
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.lattice_mu_sweeps.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double, dp, dp,
+                                        ctypes.POINTER(ctypes.c_int64)]
+        L.lattice_mu_sweeps.restype = ctypes.c_int
         L.lattice_destroy.argtypes = [vp]
         L.lattice_destroy.restype = ctypes.c_int
         L.lat_server_create.argtypes = [vp, sz, ctypes.c_int32, ctypes.c_uint64, vp, ctypes.POINTER(vp)]
@@ -253,6 +258,19 @@ class Lattice:
 
     def sweep(self, sweeps: int = 1):
         _check(lib().lattice_sweep(self.handle, sweeps))
+
+    def mu_sweeps(self, first_sweep: int, n_sweeps: int, kappa: float, mu: float):
+        """Penalty-mode sweeps (the prior method of section 2.2).  Returns (next mu,
+        mu of each sweep, sum S after each sweep)."""
+        import numpy as np
+
+        m = ctypes.c_double(mu)
+        mus = np.zeros(n_sweeps, dtype=np.float64)
+        sums = np.zeros(n_sweeps, dtype=np.int64)
+        _check(lib().lattice_mu_sweeps(self.handle, first_sweep, n_sweeps, kappa, ctypes.byref(m),
+                                       mus.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       sums.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return m.value, mus, sums
 
     def map_steps(self, first_map: int, n_maps: int = 1, partner: int = 0):
         """Apply maps first_map .. first_map+n_maps-1 of the map mode (partner MAP_ANY or MAP_NEIGHBOUR)."""

@@ -51,7 +51,11 @@ constexpr int kMaxObsSlots = 256;
 constexpr size_t kScrSlots = 24576;                   // kMaxSlots x 3 x int64 from the phase kernels
 constexpr int kMaxSlots = 1024;
 constexpr size_t kScrFullTab = kScrSlots + (size_t)kMaxSlots * 24;  // 49152: kTabSize x uint32 thresholds
-constexpr size_t kScrBytes = kScrFullTab + ((size_t)kTabSize * 4 + 255) / 256 * 256;  // 71168
+// Penalty mode: thresholds over (nD, nV, nJ, dS) of one site, nD in [-1, 1],
+// nV and nJ in [-8, 8], dS in [-2, 2], index ((nD+1)*17 + nV+8)*17 + nJ+8)*5 + dS+2.
+constexpr int kMuTabSize = 3 * 17 * 17 * 5;  // 4335
+constexpr size_t kScrMuTab = kScrFullTab + ((size_t)kTabSize * 4 + 255) / 256 * 256;  // 71168
+constexpr size_t kScrBytes = kScrMuTab + ((size_t)kMuTabSize * 4 + 255) / 256 * 256;  // 88576
 
 // Per-lattice descriptor kept in the lattice's scratch, read by the batched
 // kernel.  next_sweep is advanced on the device by every path that sweeps.
@@ -129,6 +133,16 @@ inline size_t map_lds_bytes(int L)
 }
 hipError_t launch_map_steps(const MapArgs &a, int max_L, hipStream_t s);
 hipError_t init_map_kernel_attributes();
+
+// Penalty mode: one half-sweep (checkerboard colour c) of an int8 lattice.
+struct MuArgs {
+    int8_t *state;
+    const uint32_t *tab;   // kMuTabSize thresholds (scratch + kScrMuTab)
+    unsigned long long *track;  // per-block tracker slots
+    int L, colour;
+    uint32_t key0, key1, s_lo, s_hi;
+};
+hipError_t launch_mu_half(const MuArgs &a, hipStream_t s);
 
 // One-time kernel set-up (dynamic LDS limits); called before the first launch.
 hipError_t init_kernel_attributes();

@@ -18,9 +18,12 @@ the time averages give
 and the estimate at each temperature is the mean over replicas with its
 standard error (replicas are independent chains from different seeds).
 
+The penalty mode (section 2.2's prior method) has its own scan,
+penalty_scan(), for comparison.
+
 Usage:
     python -m paper_2301_11735_amd.thermo --L 16 --n 0.1 --T 0.2 0.4 0.8 1.6 [--replicas 32]
-                                          [--sweeps 4000] [--burn 1000] [--every 1]
+                                          [--sweeps 4000] [--burn 1000] [--every 1] [--penalty --kappa 0.5]
 """
 from __future__ import annotations
 
@@ -95,6 +98,42 @@ def scan(L: int, n: float, Delta: float, V: float, J: float, temps, replicas: in
     return out
 
 
+def penalty_scan(L: int, n: float, Delta: float, V: float, J: float, temps, replicas: int = 4, sweeps: int = 2000,
+                 burn: int = 500, kappa: float = 0.5, mu0: float = 0.0, seed0: int = 1) -> list:
+    """The same estimates for the penalty mode (section 2.2, the prior method:
+    single-site updates of E - mu sum S with mu steered towards the target
+    charge after every sweep).  Replicas run one after another (the controller
+    reads the charge back every sweep); each is sampled once per sweep."""
+    N = L * L
+    out = []
+    for it, T in enumerate(temps):
+        per = {k: [] for k in ("e", "C", "nc", "q", "mu")}
+        for r in range(replicas):
+            g = lat.Lattice(L, n, Delta, V, J, float(T), seed0 + it * replicas + r, encoding=lat.ENC_INT8)
+            mu, _, _ = g.mu_sweeps(0, burn, kappa, mu0)
+            E, Nc, S, M = [], [], [], []
+            for s in range(sweeps):
+                mu, mus, sums = g.mu_sweeps(burn + s, 1, kappa, mu)
+                o = g.observables()
+                E.append(o.E)
+                Nc.append(o.n_charged)
+                S.append(sums[0])
+                M.append(mus[0])
+            g.destroy()
+            E = np.asarray(E)
+            per["e"].append(E.mean() / N)
+            per["C"].append(E.var() / (N * T * T))
+            per["nc"].append(np.mean(Nc) / N)
+            per["q"].append(np.mean(S) / N)
+            per["mu"].append(np.mean(M))
+        row = {"T": float(T), "L": L, "n": n, "Delta": Delta, "V": V, "J": J, "kappa": kappa, "replicas": replicas,
+               "samples_per_replica": sweeps, "burn": burn, "method": "penalty"}
+        for name, v in per.items():
+            row[name], row[name + "_err"] = _mean_err(v)
+        out.append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--L", type=int, default=16)
@@ -108,10 +147,17 @@ def main():
     ap.add_argument("--burn", type=int, default=1000)
     ap.add_argument("--every", type=int, default=1)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--penalty", action="store_true",
+                    help="also scan the penalty mode (section 2.2) with --kappa, 4 replicas")
+    ap.add_argument("--kappa", type=float, default=0.5)
     args = ap.parse_args()
     for row in scan(args.L, args.n, args.Delta, args.V, args.J, args.T, args.replicas, args.sweeps, args.burn,
                     args.every, args.seed):
         print(json.dumps(row), flush=True)
+    if args.penalty:
+        for row in penalty_scan(args.L, args.n, args.Delta, args.V, args.J, args.T, 4, args.sweeps, args.burn,
+                                args.kappa, seed0=args.seed):
+            print(json.dumps(row), flush=True)
 
 
 if __name__ == "__main__":

@@ -122,3 +122,9 @@ def test_map_calls_on_null_handles_fail_cleanly():
     assert L.lattice_map_steps_batch(None, 0, 0, 1, 7, None) == lat.LAT_EINVAL
     fake = (ctypes.c_void_p * 1)(None)
     assert L.lattice_map_steps_batch(fake, 1, 0, 1, 1, None) == lat.LAT_ESTATE
+
+
+def test_penalty_calls_on_null_handles_fail_cleanly():
+    L = lat.lib()
+    mu = ctypes.c_double(0.0)
+    assert L.lattice_mu_sweeps(None, 0, 1, 0.5, ctypes.byref(mu), None, None) == lat.LAT_ESTATE

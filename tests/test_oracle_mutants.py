@@ -93,7 +93,8 @@ def _pin_map_chain():
 
 
 MUTANTS = [
-    ("J/4 coefficient of eq. (3) dropped", "0.25 * J * nJ", "J * nJ", _pin_4x4),
+    ("J/4 coefficient of eq. (3) dropped", "double dE = Delta * nD + V * nV + 0.25 * J * nJ;",
+     "double dE = Delta * nD + V * nV + J * nJ;", _pin_4x4),
     ("bond a-b counted twice for adjacent pairs", "if (nb[k] == a) continue;", ";", _pin_pair_delta),
     ("Boltzmann factor sign flipped", "exp(-dE / T)", "exp(dE / T)", _pin_threshold),
     ("acceptance test inverted", "(u_acc < thr)", "(u_acc > thr)", _pin_4x4),
