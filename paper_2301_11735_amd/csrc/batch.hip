@@ -174,6 +174,18 @@ struct WordPhase {
 // Barrier = true keeps the compiler from interleaving the Philox calls of a
 // task (fewer live registers, needed at 1024 threads per block); without it
 // the calls overlap each other's LDS table lookups.
+// Value of the lane XOR lanes away (XOR = 1, 2: quad permutes; 4: any lane).
+template <int XOR>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v)
+{
+    if constexpr (XOR == 1)
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    else if constexpr (XOR == 2)
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    else
+        return (uint32_t)__shfl_xor((int)v, XOR, 64);
+}
+
 template <int Q, bool Barrier>
 __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uint32_t task, const uint2 *s_tab,
                                           const uint2 *s_trans, int (&tr)[3])
@@ -196,10 +208,50 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
 
     const uint32_t A0 = lat[f.oA0 + ro + j];
     const uint32_t B0 = load16(lat, f.oB0 + rob, W, Xb);
-    const SideSums sa = side_sums(load16(lat, f.oAL + ro, W, xAL), load16(lat, f.oAR + ro, W, xAR),
-                                  lat[f.oAV + roU + j], lat[f.oAV + ro + j]);
-    const SideSums sb = side_sums(load16(lat, f.oBL + rob, W, xBL), load16(lat, f.oBR + rob, W, xBR),
-                                  load16(lat, f.oBV + rob, W, Xb), load16(lat, f.oBV + robD, W, Xb));
+    SideSums sa, sb;
+    if constexpr (Q == 1) {
+        sa = side_sums(load16(lat, f.oAL + ro, W, xAL), load16(lat, f.oAR + ro, W, xAR), lat[f.oAV + roU + j],
+                       lat[f.oAV + ro + j]);
+        sb = side_sums(load16(lat, f.oBL + rob, W, xBL), load16(lat, f.oBR + rob, W, xBR),
+                       load16(lat, f.oBV + rob, W, Xb), load16(lat, f.oBV + robD, W, Xb));
+    } else {
+        // The Q threads of a word are Q consecutive lanes.  Lanes of the
+        // first half sum a-side neighbour words, the others b-side ones,
+        // 8/Q words each; the partial sums (additive, nibble-wide) are
+        // combined within the group and the two sides exchanged.
+        const int side = q >= Q / 2;
+        const int k0 = (q % (Q / 2)) * (8 / Q);
+        const uint32_t base[4] = {side ? f.oBL + rob : f.oAL + ro, side ? f.oBR + rob : f.oAR + ro,
+                                  side ? f.oBV + rob : f.oAV + roU, side ? f.oBV + robD : f.oAV + ro};
+        const int xs[4] = {side ? xBL : xAL, side ? xBR : xAR, side ? Xb : 16 * j, side ? Xb : 16 * j};
+        SideSums part{0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int i = 0; i < 8 / Q; ++i) {
+            const int kk = k0 + i;
+            const uint32_t b = kk == 0 ? base[0] : kk == 1 ? base[1] : kk == 2 ? base[2] : base[3];
+            const int x = kk == 0 ? xs[0] : kk == 1 ? xs[1] : kk == 2 ? xs[2] : xs[3];
+            side_add(part, load16(lat, b, W, x));
+        }
+        SideSums full = part, other;
+        if constexpr (Q >= 4) {
+            full.ES += lane_xor<1>(part.ES);
+            full.OS += lane_xor<1>(part.OS);
+            full.EG += lane_xor<1>(part.EG);
+            full.OG += lane_xor<1>(part.OG);
+        }
+        if constexpr (Q == 8) {
+            full.ES += lane_xor<2>(full.ES);
+            full.OS += lane_xor<2>(full.OS);
+            full.EG += lane_xor<2>(full.EG);
+            full.OG += lane_xor<2>(full.OG);
+        }
+        other.ES = lane_xor<Q / 2>(full.ES);
+        other.OS = lane_xor<Q / 2>(full.OS);
+        other.EG = lane_xor<Q / 2>(full.EG);
+        other.OG = lane_xor<Q / 2>(full.OG);
+        sa = side ? other : full;
+        sb = side ? full : other;
+    }
 
     const uint32_t call0 = (uint32_t)Y * (uint32_t)(Lq >> 1) + 8u * (uint32_t)j;
     uint32_t dA = 0u, dB = 0u, packed = 0u;

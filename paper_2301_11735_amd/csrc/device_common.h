@@ -161,20 +161,25 @@ struct SideSums {
     uint32_t ES, OS, EG, OG;  // nibble u: sum over neighbours of site 2u (E) or 2u+1 (O)
 };
 
+// Adds one neighbour word's 16 values to the sums.
+__device__ __forceinline__ void side_add(SideSums &s, uint32_t w)
+{
+    const uint32_t h = (w >> 1) & kM5, l = w & kM5;
+    const uint32_t vS = ((h & ~l) << 1) | (h ^ kM5);        // code 2 -> 2, 3 -> 0, spins -> 1
+    const uint32_t vG = (((h | l) ^ kM5) << 1) | h;          // code 0 -> 2, 1 -> 0, charges -> 1
+    s.ES += vS & kM3;
+    s.OS += (vS >> 2) & kM3;
+    s.EG += vG & kM3;
+    s.OG += (vG >> 2) & kM3;
+}
+
 __device__ __forceinline__ SideSums side_sums(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3)
 {
     SideSums s{0u, 0u, 0u, 0u};
-    const uint32_t ws[4] = {w0, w1, w2, w3};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t h = (ws[i] >> 1) & kM5, l = ws[i] & kM5;
-        const uint32_t vS = ((h & ~l) << 1) | (h ^ kM5);        // code 2 -> 2, 3 -> 0, spins -> 1
-        const uint32_t vG = (((h | l) ^ kM5) << 1) | h;          // code 0 -> 2, 1 -> 0, charges -> 1
-        s.ES += vS & kM3;
-        s.OS += (vS >> 2) & kM3;
-        s.EG += vG & kM3;
-        s.OG += (vG >> 2) & kM3;
-    }
+    side_add(s, w0);
+    side_add(s, w1);
+    side_add(s, w2);
+    side_add(s, w3);
     return s;
 }
 
