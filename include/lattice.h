@@ -174,9 +174,11 @@ int lattice_batch_graph_destroy(lat_batch_graph *g);
  * admits queued requests, in arrival order, into the caller's device pool when
  * a slot and pool memory are free; every call of lat_server_step advances all
  * resident requests together in one batched launch (section 3.2: lattice
- * copies processed together), each by about `quantum_updates` site updates
- * (max(1, quantum_updates / N) sweeps, capped by what the request still
- * needs), then harvests the finished ones and frees their memory, so new
+ * copies processed together), each by about the same time on its compute
+ * unit: max(1, quantum_updates / (N + 11000)) sweeps, capped by what the
+ * request still needs (a sweep costs about N + 11000 site-update times, the
+ * constant being its fixed per-phase cost), then harvests the finished ones
+ * and frees their memory, so new
  * requests join between steps.  A request's result is bit-identical to
  * running it alone with lattice_create/lattice_sweep.  Served lattices need
  * L <= 512.  Timestamps are seconds of the monotonic clock (CLOCK_MONOTONIC).

@@ -3,11 +3,16 @@
 // are free, advance together (one batched launch per step, continuous
 // batching: new requests join between steps), and are harvested when done.
 //
-// Each step gives every resident lattice about the same amount of work:
-// max(1, quantum / N) sweeps, capped by what the request still needs, so a
-// launch is not held up by the largest lattice.  Results are bit-identical to
-// running the same request alone: a lattice's chain depends only on its
-// parameters, seed and sweep index.
+// Each step gives every resident lattice about the same time on its compute
+// unit: a sweep of N sites costs about (N + kSweepCostSites) site-update
+// times (a fixed part -- four phase barriers and the latency of a phase's
+// dependent LDS reads -- plus a part proportional to N; on MI355X the fixed
+// part is worth about 11,000 site updates), so a lattice gets
+// max(1, quantum / (N + kSweepCostSites)) sweeps, capped by what the request
+// still needs.  Blocks then end together, so a step is not held up by small
+// lattices doing many cheap sweeps and large requests advance at their full
+// rate.  Results are bit-identical to running the same request alone: a
+// lattice's chain depends only on its parameters, seed and sweep index.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,6 +34,7 @@ using namespace lat::detail;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr uint64_t kSweepCostSites = 11000;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -206,7 +212,7 @@ int lat_server_step(lat_server *s, int32_t *n_finished)
     for (uint64_t id : s->resident) {
         Request &r = *s->reqs[id];
         const uint64_t N = (uint64_t)r.params.L * r.params.L;
-        const uint32_t want = (uint32_t)std::max<uint64_t>(1, s->quantum / N);
+        const uint32_t want = (uint32_t)std::max<uint64_t>(1, s->quantum / (N + kSweepCostSites));
         const uint32_t k = std::min(want, r.sweeps - r.done);
         hs.push_back(r.h);
         sw.push_back(k);
