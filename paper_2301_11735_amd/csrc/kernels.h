@@ -118,19 +118,22 @@ hipError_t launch_observables(uint8_t *scratch, const void *state, int L, int en
 // per lattice holding the codes (one byte per site), the map's mark bitmap,
 // its pair list and the full threshold table in LDS.
 constexpr int kMapMaxL = 256;
-constexpr int kMapThreads = 256;
+constexpr int kMapThreads = 512;
 struct MapArgs {
     int count;
     uint8_t *scratch[kMaxBatch];
     uint32_t first_map_lo, first_map_hi, n_maps;
-    int32_t nn;  // 1: nearest-neighbour partners, max(1, N/20) pairs per map
+    int32_t nn;        // 1: nearest-neighbour partners, max(1, N/20) pairs per map
+    int32_t builders;  // maps built at once (one per wave), each with its own bitmap and pair list
 };
-// LDS bytes one block needs for a lattice of side L.
-inline size_t map_lds_bytes(int L)
+// LDS bytes one block needs for a lattice of side L with `builders` maps in flight.
+inline size_t map_lds_bytes(int L, int builders)
 {
     const size_t N = (size_t)L * L, pairs = N / 10 < 1 ? 1 : N / 10;
-    return (size_t)kTabSize * 4 + (N + 3) / 4 * 4 + (N + 31) / 32 * 4 + pairs * 4;
+    return (size_t)kTabSize * 4 + (N + 3) / 4 * 4 + (size_t)builders * ((N + 31) / 32 * 4 + pairs * 4);
 }
+// Dynamic LDS a map block may use (160 KiB per workgroup, less the static reduction buffer).
+constexpr size_t kMapLdsMax = 160 * 1024 - 1024;
 hipError_t launch_map_steps(const MapArgs &a, int max_L, hipStream_t s);
 hipError_t init_map_kernel_attributes();
 

@@ -56,7 +56,7 @@ template <bool NN>
 __device__ void build_map(uint32_t *bitmap, uint32_t *pairs, int L, uint32_t N, uint32_t n_pairs, uint32_t m_lo,
                           uint32_t m_hi, uint32_t key0, uint32_t key1)
 {
-    const uint32_t lane = threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63u;
     uint32_t k = 0, count = 0, need_b = 0, a_site = 0;
     uint32_t an[4] = {0u, 0u, 0u, 0u};  // neighbours of the pending first site
     while (count < n_pairs) {
@@ -194,10 +194,12 @@ __global__ void __launch_bounds__(kMapThreads) k_map_steps(MapArgs args)
     const uint32_t N = (uint32_t)L * (uint32_t)L;
     const uint32_t per = args.nn ? 20u : 10u;
     const uint32_t n_pairs = N / per < 1u ? 1u : N / per;
+    const uint32_t G = (uint32_t)args.builders;            // maps built at once, one per wave
+    const uint32_t bwords = (N + 31u) / 32u;
     uint32_t *thr = smem;                                   // kTabSize
     uint8_t *codes = (uint8_t *)(smem + kTabSize);          // N bytes
-    uint32_t *bitmap = smem + kTabSize + (N + 3u) / 4u;     // ceil(N/32) words
-    uint32_t *pairs = bitmap + (N + 31u) / 32u;             // n_pairs
+    uint32_t *bitmaps = smem + kTabSize + (N + 3u) / 4u;    // G x bwords
+    uint32_t *pairs = bitmaps + G * bwords;                 // G x n_pairs
 
     const uint32_t *g_thr = (const uint32_t *)(scr + kScrFullTab);
     for (uint32_t i = threadIdx.x; i < (uint32_t)kTabSize; i += blockDim.x) thr[i] = g_thr[i];
@@ -218,29 +220,39 @@ __global__ void __launch_bounds__(kMapThreads) k_map_steps(MapArgs args)
 
     int tr[3] = {0, 0, 0};
     const uint64_t first = ((uint64_t)args.first_map_hi << 32) | args.first_map_lo;
-    for (uint32_t mi = 0; mi < args.n_maps; ++mi) {
-        const uint64_t m = first + mi;
-        const uint32_t m_lo = (uint32_t)m, m_hi = (uint32_t)(m >> 32);
-        for (uint32_t i = threadIdx.x; i < (N + 31u) / 32u; i += blockDim.x) bitmap[i] = 0u;
+    const uint32_t wave = threadIdx.x >> 6;
+    for (uint32_t m0 = 0; m0 < args.n_maps; m0 += G) {
+        const uint32_t group = min(G, args.n_maps - m0);
+        // maps depend only on the seed and their index: build `group` of them at once
+        for (uint32_t i = threadIdx.x; i < group * bwords; i += blockDim.x) bitmaps[i] = 0u;
         __syncthreads();
-        if (threadIdx.x < 64) {
+        if (wave < group) {
+            const uint64_t m = first + m0 + wave;
             if (args.nn)
-                build_map<true>(bitmap, pairs, L, N, n_pairs, m_lo, m_hi, d.key0, d.key1);
+                build_map<true>(bitmaps + wave * bwords, pairs + wave * n_pairs, L, N, n_pairs, (uint32_t)m,
+                                (uint32_t)(m >> 32), d.key0, d.key1);
             else
-                build_map<false>(bitmap, pairs, L, N, n_pairs, m_lo, m_hi, d.key0, d.key1);
+                build_map<false>(bitmaps + wave * bwords, pairs + wave * n_pairs, L, N, n_pairs, (uint32_t)m,
+                                 (uint32_t)(m >> 32), d.key0, d.key1);
         }
         __syncthreads();
-        // pairs 2c and 2c+1 share Philox call c
-        for (uint32_t c = threadIdx.x; 2u * c < n_pairs; c += blockDim.x) {
-            const u32x4 w = philox4x32_10(m_lo, kDomMapStep, c, m_hi, d.key0, d.key1);
-            const uint32_t p0 = pairs[2u * c];
-            map_pair_step(codes, thr, L, p0 & 0xFFFFu, p0 >> 16, w.x, w.y, tr);
-            if (2u * c + 1u < n_pairs) {
-                const uint32_t p1 = pairs[2u * c + 1u];
-                map_pair_step(codes, thr, L, p1 & 0xFFFFu, p1 >> 16, w.z, w.w, tr);
+        // ...then apply them in map order
+        for (uint32_t g = 0; g < group; ++g) {
+            const uint64_t m = first + m0 + g;
+            const uint32_t m_lo = (uint32_t)m, m_hi = (uint32_t)(m >> 32);
+            const uint32_t *mp = pairs + g * n_pairs;
+            // pairs 2c and 2c+1 share Philox call c
+            for (uint32_t c = threadIdx.x; 2u * c < n_pairs; c += blockDim.x) {
+                const u32x4 w = philox4x32_10(m_lo, kDomMapStep, c, m_hi, d.key0, d.key1);
+                const uint32_t p0 = mp[2u * c];
+                map_pair_step(codes, thr, L, p0 & 0xFFFFu, p0 >> 16, w.x, w.y, tr);
+                if (2u * c + 1u < n_pairs) {
+                    const uint32_t p1 = mp[2u * c + 1u];
+                    map_pair_step(codes, thr, L, p1 & 0xFFFFu, p1 >> 16, w.z, w.w, tr);
+                }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     if (d.enc == 0) {
@@ -264,14 +276,23 @@ __global__ void __launch_bounds__(kMapThreads) k_map_steps(MapArgs args)
 
 hipError_t launch_map_steps(const MapArgs &a, int max_L, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_map_steps, dim3((unsigned)a.count), dim3(kMapThreads), map_lds_bytes(max_L), s, a);
+    // as many concurrent builders (at most one per wave) as LDS allows
+    MapArgs b = a;
+    b.builders = 1;
+    for (int g = kMapThreads / 64; g > 1; g /= 2)
+        if (map_lds_bytes(max_L, g) <= kMapLdsMax) {
+            b.builders = g;
+            break;
+        }
+    hipLaunchKernelGGL(k_map_steps, dim3((unsigned)b.count), dim3(kMapThreads), map_lds_bytes(max_L, b.builders), s,
+                       b);
     return hipGetLastError();
 }
 
 hipError_t init_map_kernel_attributes()
 {
     return hipFuncSetAttribute((const void *)k_map_steps, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)map_lds_bytes(kMapMaxL));
+                               (int)kMapLdsMax);
 }
 
 }  // namespace lat
