@@ -144,6 +144,17 @@ __device__ __forceinline__ void device_schedule(int L, uint32_t k0, uint32_t k1,
     }
 }
 
+// The two words of the class row at word offset `row` that hold the 16 sites
+// starting at class position xs (periodic); alignbit(hi, lo, 2 (xs mod 16))
+// then gives the 16 sites (a shift of 0 gives lo).
+__device__ __forceinline__ void load_pair(const uint32_t *__restrict__ st, uint32_t row, int W, int xs, uint32_t &lo,
+                                          uint32_t &hi)
+{
+    const int jw = xs >> 4;
+    lo = st[row + (uint32_t)jw];
+    hi = st[row + (uint32_t)(jw + 1 == W ? 0 : jw + 1)];
+}
+
 // 16 sites of the class row at word offset `row` of `st`, starting at class
 // position xs (periodic).  32-bit offsets keep the base pointer uniform.
 __device__ __forceinline__ uint32_t load16(const uint32_t *__restrict__ st, uint32_t row, int W, int xs)

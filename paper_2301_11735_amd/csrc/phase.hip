@@ -87,8 +87,13 @@ __global__ void __launch_bounds__(256) k_phase_int8(PhaseArgs a)
 // The ten words one thread reads for its 16 pairs: its a-word, the a-words'
 // left/right/up/down neighbour words, and the same five for the 16 partners
 // (the b-side words start mid-word and are funnel-shifted into place).
+// Seven of them start mid-word (by the same shift for every thread of a
+// phase): both words covering each are fetched, and the funnel shift into
+// place waits until the group is computed, so a prefetch never waits for its
+// own loads.
 struct PairWords {
-    uint32_t A0, AL, AR, AU, AD, B0, BL, BR, BU, BD;
+    uint32_t A0, AU, AD;
+    uint32_t ALlo, ALhi, ARlo, ARhi, B0lo, B0hi, BLlo, BLhi, BRlo, BRhi, BUlo, BUhi, BDlo, BDhi;
 };
 
 // One phase of the 2-bit lattice by this block: row groups blockIdx.x,
@@ -134,17 +139,20 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
         const uint32_t robD = (uint32_t)(Yb + 1 == H ? 0 : Yb + 1) * W;
         PairWords w;
         w.A0 = st[oA0 + ro + j];
-        w.AL = load16(st, oAL + ro, W, xAL);
-        w.AR = load16(st, oAR + ro, W, xAR);
         w.AU = st[oAV + roU + j];
         w.AD = st[oAV + ro + j];
-        w.B0 = load16(st, oB0 + rob, W, Xb);
-        w.BL = load16(st, oBL + rob, W, xBL);
-        w.BR = load16(st, oBR + rob, W, xBR);
-        w.BU = load16(st, oBV + rob, W, Xb);
-        w.BD = load16(st, oBV + robD, W, Xb);
+        load_pair(st, oAL + ro, W, xAL, w.ALlo, w.ALhi);
+        load_pair(st, oAR + ro, W, xAR, w.ARlo, w.ARhi);
+        load_pair(st, oB0 + rob, W, Xb, w.B0lo, w.B0hi);
+        load_pair(st, oBL + rob, W, xBL, w.BLlo, w.BLhi);
+        load_pair(st, oBR + rob, W, xBR, w.BRlo, w.BRhi);
+        load_pair(st, oBV + rob, W, Xb, w.BUlo, w.BUhi);
+        load_pair(st, oBV + robD, W, Xb, w.BDlo, w.BDhi);
         return w;
     };
+    // funnel shifts (uniform per phase: 2 * (x mod 16) for each start x)
+    const uint32_t fAL = 2u * (uint32_t)(xAL & 15), fAR = 2u * (uint32_t)(xAR & 15);
+    const uint32_t fB = 2u * (uint32_t)(Xb & 15), fBL = 2u * (uint32_t)(xBL & 15), fBR = 2u * (uint32_t)(xBR & 15);
 
     // Each group's words are fetched before the previous group is computed.
     // Every word read is either never written in this phase or written only
@@ -159,15 +167,20 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
         if (gn < n_groups) nxt = load_words(gn);
         const int Y = row_of(g), Yb = brow_of(Y);
 
-        const SideSums sa = side_sums(cur.AL, cur.AR, cur.AU, cur.AD);
-        const SideSums sb = side_sums(cur.BL, cur.BR, cur.BU, cur.BD);
+        const uint32_t B0 = __builtin_amdgcn_alignbit(cur.B0hi, cur.B0lo, fB);
+        const SideSums sa = side_sums(__builtin_amdgcn_alignbit(cur.ALhi, cur.ALlo, fAL),
+                                      __builtin_amdgcn_alignbit(cur.ARhi, cur.ARlo, fAR), cur.AU, cur.AD);
+        const SideSums sb = side_sums(__builtin_amdgcn_alignbit(cur.BLhi, cur.BLlo, fBL),
+                                      __builtin_amdgcn_alignbit(cur.BRhi, cur.BRlo, fBR),
+                                      __builtin_amdgcn_alignbit(cur.BUhi, cur.BUlo, fB),
+                                      __builtin_amdgcn_alignbit(cur.BDhi, cur.BDlo, fB));
         // bpack of site t = (sumS_a+4, sumS_b+4, sumsig_a+4, sumsig_b+4): site
         // t = 4k + g is byte k of nibble plane g (g = 0, 2: even sites, low and
         // high nibbles; g = 1, 3: odd sites).  Philox call c serves t = 2c and
         // 2c+1, so calls 0,2,4,6 need planes 0 and 1, calls 1,3,5,7 planes 2
         // and 3; handling them in that order keeps 8 packed words live.
         uint32_t Anew = 0u, Bnew = 0u, packed = 0u;
-        const uint32_t kq2w = word_kq2(cur.A0, cur.B0);
+        const uint32_t kq2w = word_kq2(cur.A0, B0);
         const uint32_t call0 = (uint32_t)Y * (uint32_t)(Lq >> 1) + 8u * (uint32_t)j;
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
@@ -185,7 +198,7 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int t = 2 * c + h;
-                    const uint32_t s0 = ((cur.A0 >> (2 * t)) & 3u) | (((cur.B0 >> (2 * t)) & 3u) << 2);
+                    const uint32_t s0 = ((cur.A0 >> (2 * t)) & 3u) | (((B0 >> (2 * t)) & 3u) << 2);
                     const uint32_t ns = pair_step_k2(s0, (kq2w >> (2 * t)) & 3u, h ? go[k] : ge[k], h ? w.z : w.x,
                                                      h ? w.w : w.y, s_trans, s_tab, packed);
                     Anew |= (ns & 3u) << (2 * t);
