@@ -75,6 +75,23 @@ __device__ __forceinline__ uint32_t pair_step_k2(uint32_t st, uint32_t kq2, uint
     return acc ? (tr.y >> 16) : st;
 }
 
+// The same step with the delta form of the transition table: an accepted
+// move ORs its code changes into dacc at the fields that `fields` selects
+// (the pair's 2-bit field in the low half for site a and in the high half for
+// site b); the caller XORs the accumulated changes into the codes.
+__device__ __forceinline__ void pair_step_delta(uint32_t st, uint32_t kq2, uint32_t bpack, uint32_t uc, uint32_t ua,
+                                                const uint4 *__restrict__ s_transd, const uint2 *__restrict__ s_tab,
+                                                uint32_t fields, uint32_t &packed, uint32_t &dacc)
+{
+    const uint32_t j = ((uc >> 8) * kq2) >> 23;
+    const uint4 tr = s_transd[st * 6u + j];
+    const int idx = __builtin_amdgcn_sdot4((int)tr.x, (int)bpack, (int)tr.y, false);
+    const uint2 e = s_tab[idx];
+    const bool acc = min(ua, 0xFFFFFFFEu) < e.x;
+    packed += acc ? e.y : 0u;
+    dacc |= tr.z & (acc ? fields : 0u);
+}
+
 __device__ __forceinline__ uint32_t pair_step(uint32_t st, uint32_t bpack, uint32_t uc, uint32_t ua,
                                               const uint2 *__restrict__ s_trans, const uint2 *__restrict__ s_tab,
                                               uint32_t &packed)
@@ -91,26 +108,78 @@ __device__ __forceinline__ void unpack_tracker(uint32_t packed, int (&tr)[3])
     tr[2] += (int)(packed & 1023u) - 16 * cnt;
 }
 
+// Wave-wide sum by DPP (row reductions, then row broadcasts 15 and 31): the
+// total ends in lane 63 and is returned to every lane.  Every lane of the
+// wave must be active.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ int dpp_i32(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, Ctrl, RowMask, 0xF, false);
+}
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ long long dpp_i64(long long v)
+{
+    const int lo = dpp_i32<Ctrl, RowMask>((int)(uint32_t)v), hi = dpp_i32<Ctrl, RowMask>((int)((uint64_t)v >> 32));
+    return (long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ int dpp_step_sum(int v)
+{
+    v += dpp_i32<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v += dpp_i32<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v += dpp_i32<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp_i32<0x140, 0xF>(v);  // row_mirror
+    v += dpp_i32<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_i32<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ long long dpp_step_sum(long long v)
+{
+    v += dpp_i64<0xB1, 0xF>(v);
+    v += dpp_i64<0x4E, 0xF>(v);
+    v += dpp_i64<0x141, 0xF>(v);
+    v += dpp_i64<0x140, 0xF>(v);
+    v += dpp_i64<0x142, 0xA>(v);
+    v += dpp_i64<0x143, 0xC>(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)((uint64_t)v >> 32), 63);
+    return (long long)(((uint64_t)hi << 32) | lo);
+}
+
+// Per-wave sums of K values, written to part[wave][*] by lane 0.  Full
+// waves (blockDim a multiple of 64, the launch shapes of the sweep kernels)
+// reduce by DPP; a partial wave falls back to shuffles.
+template <int K, typename T>
+__device__ __forceinline__ void wave_partials(T (&v)[K], T (*part)[K])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if ((blockDim.x & 63u) == 0) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) v[i] = dpp_step_sum(v[i]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < K; ++i) part[wave][i] = v[i];
+}
+
+// Block-level sum of K values added to dst[0..K): thread i < K sums value i
+// over the block's waves and adds it with one atomic.
 template <int K, typename T>
 __device__ __forceinline__ void block_reduce_add(T (&v)[K], unsigned long long *dst)
 {
     __shared__ T part[16][K];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < K; ++i)
-        for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
-    if (lane == 0)
-#pragma unroll
-        for (int i = 0; i < K; ++i) part[wave][i] = v[i];
+    wave_partials<K, T>(v, part);
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < K) {
         const int nw = (blockDim.x + 63) >> 6;
+        long long s = 0;
 #pragma unroll
-        for (int i = 0; i < K; ++i) {
-            long long s = 0;
-            for (int w = 0; w < nw; ++w) s += (long long)part[w][i];
-            if (s != 0) atomicAdd(&dst[i], (unsigned long long)s);
-        }
+        for (int w = 0; w < 16; ++w)
+            if (w < nw) s += (long long)part[w][threadIdx.x];
+        if (s != 0) atomicAdd(&dst[threadIdx.x], (unsigned long long)s);
     }
 }
 
@@ -225,19 +294,15 @@ __device__ __forceinline__ int charge_of(uint32_t c) { return (c & 2u) ? 1 - 2 *
 template <int K, typename T>
 __device__ __forceinline__ void block_reduce_store(T (&v)[K], long long *dst)
 {
-    __shared__ long long part[16][K];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < K; ++i)
-        for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
-    if (lane == 0)
-#pragma unroll
-        for (int i = 0; i < K; ++i) part[wave][i] = (long long)v[i];
+    __shared__ T part[16][K];
+    wave_partials<K, T>(v, part);
     __syncthreads();
     if (threadIdx.x < K) {
         const int nw = (blockDim.x + 63) >> 6;
         long long s = 0;
-        for (int w = 0; w < nw; ++w) s += part[w][threadIdx.x];
+#pragma unroll
+        for (int w = 0; w < 16; ++w)
+            if (w < nw) s += (long long)part[w][threadIdx.x];
         dst[threadIdx.x] = s;
     }
 }

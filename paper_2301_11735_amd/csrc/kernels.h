@@ -55,7 +55,15 @@ constexpr size_t kScrFullTab = kScrSlots + (size_t)kMaxSlots * 24;  // 49152: kT
 // nV and nJ in [-8, 8], dS in [-2, 2], index ((nD+1)*17 + nV+8)*17 + nJ+8)*5 + dS+2.
 constexpr int kMuTabSize = 3 * 17 * 17 * 5;  // 4335
 constexpr size_t kScrMuTab = kScrFullTab + ((size_t)kTabSize * 4 + 255) / 256 * 256;  // 71168
-constexpr size_t kScrBytes = kScrMuTab + ((size_t)kMuTabSize * 4 + 255) / 256 * 256;  // 88576
+// Delta form of the transition table, read by the 2-bit phase kernel: entry
+// st*6 + j is {coef, C, R, 0} with coef and C as in the transition table and
+// R = (d_a * 0x5555) | (d_b * 0x5555) << 16, where d_a and d_b are the XOR of
+// the new and the old code of site a and of site b: every 2-bit field of the
+// low half holds d_a and every field of the high half d_b, so that one AND
+// with a field mask places an accepted move's code changes at any pair
+// position.
+constexpr size_t kScrTransD = kScrMuTab + ((size_t)kMuTabSize * 4 + 255) / 256 * 256;  // 88576
+constexpr size_t kScrBytes = kScrTransD + (size_t)kTransEntries * 16;                 // 90112
 
 // Per-lattice descriptor kept in the lattice's scratch, read by the batched
 // kernel.  next_sweep is advanced on the device by every path that sweeps.
@@ -84,6 +92,7 @@ struct PhaseArgs {
     void *state;
     const uint2 *dev_tab;    // kDevTabEntries
     const uint2 *trans;      // kTransEntries
+    const uint4 *trans_d;    // kTransEntries, delta form
     unsigned long long *track;  // tracker slots: block b adds its 3 sums at track[3b..3b+2]
     int L;
     int p, r, m, k;

@@ -187,14 +187,15 @@ void build_device_table(const std::vector<uint32_t> &tab, std::vector<uint32_t> 
 // the device-table index of the move's (nD, nV, nJ).  Since the pair keeps its
 // charge, dS_a + dS_b = 0 and the +4 offsets of the charge sums cancel; the
 // spin offsets 4*(dsig_a + dsig_b) are folded into C.  The frozen states
-// (|q| = 2) get one null move.
-void build_transition_table(std::vector<uint32_t> &trans)
+// (|q| = 2) get one null move.  trans_d is the delta form (4 words an entry).
+void build_transition_table(std::vector<uint32_t> &trans, std::vector<uint32_t> &trans_d)
 {
     static const int kS[4] = {0, 0, 1, -1}, kG[4] = {1, -1, 0, 0};
     static const int kPlus1[4][2] = {{2, 0}, {2, 1}, {0, 2}, {1, 2}};
     static const int kZero[6][2] = {{2, 3}, {3, 2}, {0, 0}, {1, 1}, {0, 1}, {1, 0}};
     static const int kMinus1[4][2] = {{3, 0}, {3, 1}, {0, 3}, {1, 3}};
     trans.assign(2 * (size_t)kTransEntries, 0u);
+    trans_d.assign(4 * (size_t)kTransEntries, 0u);
     auto i8 = [](int v) { return (uint32_t)(uint8_t)(int8_t)v; };
     for (int st = 0; st < 16; ++st) {
         const int ca = st & 3, cb = st >> 2, q = kS[ca] + kS[cb];
@@ -219,6 +220,11 @@ void build_transition_table(std::vector<uint32_t> &trans)
             }
             trans[2 * (size_t)(st * 6 + j)] = coef;
             trans[2 * (size_t)(st * 6 + j) + 1] = (uint32_t)C | ((uint32_t)(a1 | (b1 << 2)) << 16);
+            uint32_t *d = &trans_d[4 * (size_t)(st * 6 + j)];
+            d[0] = coef;
+            d[1] = (uint32_t)C;
+            d[2] = (uint32_t)(a1 ^ ca) * 0x5555u | ((uint32_t)(b1 ^ cb) * 0x5555u) << 16;
+            d[3] = 0u;
         }
     }
 }
@@ -307,6 +313,7 @@ int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
     a.state = h->d_state;
     a.dev_tab = (const uint2 *)(h->d_scratch + kScrDevTab);
     a.trans = (const uint2 *)(h->d_scratch + kScrTrans);
+    a.trans_d = (const uint4 *)(h->d_scratch + kScrTransD);
     a.track = (unsigned long long *)(h->d_scratch + kScrSlots);
     a.L = h->L;
     a.key0 = (uint32_t)h->seed;
@@ -586,10 +593,10 @@ int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void 
     }
     std::vector<uint8_t> dev;
     to_device_layout(p->L, p->encoding, codes, dev);
-    std::vector<uint32_t> tab, dev_tab, trans;
+    std::vector<uint32_t> tab, dev_tab, trans, trans_d;
     build_threshold_table(p->Delta, p->V, p->J, p->T, tab);
     build_device_table(tab, dev_tab);
-    build_transition_table(trans);
+    build_transition_table(trans, trans_d);
     {
         static std::once_flag once;
         static hipError_t init_err = hipSuccess;
@@ -636,6 +643,9 @@ int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void 
                            h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->d_scratch + kScrTrans, trans.data(), trans.size() * 4, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->d_scratch + kScrTransD, trans_d.data(), trans_d.size() * 4, hipMemcpyHostToDevice,
+                           h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->d_scratch + kScrFullTab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)

@@ -18,6 +18,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 
@@ -96,12 +97,33 @@ struct PairWords {
     uint32_t ALlo, ALhi, ARlo, ARhi, B0lo, B0hi, BLlo, BLhi, BRlo, BRhi, BUlo, BUhi, BDlo, BDhi;
 };
 
-// One phase of the 2-bit lattice by this block: row groups blockIdx.x,
-// blockIdx.x + gridDim.x, ...  The tables are already staged in LDS.
-__device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_block, const uint2 *__restrict__ s_tab,
-                                           const uint2 *__restrict__ s_trans, uint32_t *xch, int (&tr)[3])
-{
+// LDS tables of the 2-bit phase kernels, in 8-byte units: the device
+// threshold table, one pad entry, the delta transition table (16-byte
+// aligned), and one spare entry that absorbs the writes of threads past the
+// end during staging.
+constexpr int kLdsTransD = kDevTabEntries + 1;                // 934: 16-byte aligned
+constexpr int kLdsTabUnits = kLdsTransD + 2 * kTransEntries;  // 1126
+static_assert((kLdsTransD * 8) % 16 == 0, "delta table alignment");
 
+__device__ __forceinline__ uint2 table_unit(const PhaseArgs &a, int i)
+{
+    return i < kLdsTransD ? a.dev_tab[min(i, kDevTabEntries - 1)]
+                          : ((const uint2 *)a.trans_d)[i - kLdsTransD];
+}
+
+// One phase of the 2-bit lattice by this block: row groups blockIdx.x,
+// blockIdx.x + gridDim.x, ...
+//
+// s_tabs holds kLdsTabUnits + 1 entries.  Stage false: the tables are
+// already there.  Stage true: they are copied here; the table loads are
+// issued first, then the first group's words, so that the LDS writes wait
+// only for the former and the word loads overlap the staging.
+template <bool Stage>
+__device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_block, uint2 *s_tabs, uint32_t *xch,
+                                           int (&tr)[3])
+{
+    const uint2 *s_tab = s_tabs;
+    const uint4 *s_transd = (const uint4 *)(s_tabs + kLdsTransD);
     const int L = a.L, W = L >> 6, H = L >> 1, Lq = L >> 2;
     const int rr = threadIdx.x / W, j = threadIdx.x - rr * W;
     const int n_groups = H / rows_per_block;
@@ -154,34 +176,36 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
     const uint32_t fAL = 2u * (uint32_t)(xAL & 15), fAR = 2u * (uint32_t)(xAR & 15);
     const uint32_t fB = 2u * (uint32_t)(Xb & 15), fBL = 2u * (uint32_t)(xBL & 15), fBR = 2u * (uint32_t)(xBR & 15);
 
-    // Each group's words are fetched before the previous group is computed.
-    // Every word read is either never written in this phase or written only
-    // by this block in the iteration that owns it, after its read.
-    int g = blockIdx.x;
-    PairWords cur{};
-    if (g < n_groups) cur = load_words(g);
-    int buf = 0;
-    for (; g < n_groups; g += gridDim.x, buf ^= 1) {
-        const int gn = g + gridDim.x;
-        PairWords nxt{};
-        if (gn < n_groups) nxt = load_words(gn);
-        const int Y = row_of(g), Yb = brow_of(Y);
-
-        const uint32_t B0 = __builtin_amdgcn_alignbit(cur.B0hi, cur.B0lo, fB);
-        const SideSums sa = side_sums(__builtin_amdgcn_alignbit(cur.ALhi, cur.ALlo, fAL),
-                                      __builtin_amdgcn_alignbit(cur.ARhi, cur.ARlo, fAR), cur.AU, cur.AD);
-        const SideSums sb = side_sums(__builtin_amdgcn_alignbit(cur.BLhi, cur.BLlo, fBL),
-                                      __builtin_amdgcn_alignbit(cur.BRhi, cur.BRlo, fBR),
-                                      __builtin_amdgcn_alignbit(cur.BUhi, cur.BUlo, fB),
-                                      __builtin_amdgcn_alignbit(cur.BDhi, cur.BDlo, fB));
+    // Draws of the group's 8 Philox calls (call c serves pairs 2c and 2c+1).
+    auto call_of = [&](int gg, int c) {
+        const uint32_t call0 = (uint32_t)row_of(gg) * (uint32_t)(Lq >> 1) + 8u * (uint32_t)j;
+        return philox4x32_10(a.s_lo, (uint32_t)p, call0 + (uint32_t)c, a.s_hi, a.key0, a.key1);
+    };
+    // Updates the 16 pairs of group gg from its words cw.  Pre: the draws of
+    // the even calls (used first) are given in pre[] (computed while the
+    // group's words were in flight); otherwise each call is made where its
+    // pairs need it.
+    auto group = [&](auto pre_tag, const PairWords &cw, int gg, int bb, const u32x4 (&pre)[4], auto &&prefetch) {
+        constexpr bool kPre = decltype(pre_tag)::value;
+        if (!kPre) prefetch();
+        const int Y = row_of(gg), Yb = brow_of(Y);
+        const uint32_t B0 = __builtin_amdgcn_alignbit(cw.B0hi, cw.B0lo, fB);
+        const SideSums sa = side_sums(__builtin_amdgcn_alignbit(cw.ALhi, cw.ALlo, fAL),
+                                      __builtin_amdgcn_alignbit(cw.ARhi, cw.ARlo, fAR), cw.AU, cw.AD);
+        const SideSums sb = side_sums(__builtin_amdgcn_alignbit(cw.BLhi, cw.BLlo, fBL),
+                                      __builtin_amdgcn_alignbit(cw.BRhi, cw.BRlo, fBR),
+                                      __builtin_amdgcn_alignbit(cw.BUhi, cw.BUlo, fB),
+                                      __builtin_amdgcn_alignbit(cw.BDhi, cw.BDlo, fB));
         // bpack of site t = (sumS_a+4, sumS_b+4, sumsig_a+4, sumsig_b+4): site
         // t = 4k + g is byte k of nibble plane g (g = 0, 2: even sites, low and
         // high nibbles; g = 1, 3: odd sites).  Philox call c serves t = 2c and
         // 2c+1, so calls 0,2,4,6 need planes 0 and 1, calls 1,3,5,7 planes 2
         // and 3; handling them in that order keeps 8 packed words live.
-        uint32_t Anew = 0u, Bnew = 0u, packed = 0u;
-        const uint32_t kq2w = word_kq2(cur.A0, B0);
-        const uint32_t call0 = (uint32_t)Y * (uint32_t)(Lq >> 1) + 8u * (uint32_t)j;
+        uint32_t dlo = 0u, dhi = 0u, packed = 0u;  // code changes of pairs 0-7 and 8-15
+        const uint32_t kq2w = word_kq2(cw.A0, B0);
+        // with the draws held in registers, the next group's words are
+        // fetched once this group's neighbour words are consumed
+        if (kPre) prefetch();
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             uint32_t ge[4], go[4];
@@ -193,16 +217,14 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int c = 2 * k + half;
-                const u32x4 w =
-                    philox4x32_10(a.s_lo, (uint32_t)p, call0 + (uint32_t)c, a.s_hi, a.key0, a.key1);
+                const u32x4 w = (kPre && half == 0) ? pre[k] : call_of(gg, c);
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int t = 2 * c + h;
-                    const uint32_t s0 = ((cur.A0 >> (2 * t)) & 3u) | (((B0 >> (2 * t)) & 3u) << 2);
-                    const uint32_t ns = pair_step_k2(s0, (kq2w >> (2 * t)) & 3u, h ? go[k] : ge[k], h ? w.z : w.x,
-                                                     h ? w.w : w.y, s_trans, s_tab, packed);
-                    Anew |= (ns & 3u) << (2 * t);
-                    Bnew |= (ns >> 2) << (2 * t);
+                    const uint32_t s0 = ((cw.A0 >> (2 * t)) & 3u) | (((B0 >> (2 * t)) & 3u) << 2);
+                    const uint32_t fields = 0x00030003u << (2 * (t & 7));
+                    pair_step_delta(s0, (kq2w >> (2 * t)) & 3u, h ? go[k] : ge[k], h ? w.z : w.x, h ? w.w : w.y,
+                                    s_transd, s_tab, fields, packed, t < 8 ? dlo : dhi);
                 }
                 // keep the scheduler from hoisting every Philox call at once
                 // (register pressure decides how many waves fit per SIMD)
@@ -210,13 +232,69 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
             }
         }
         unpack_tracker(packed, tr);
+        const uint32_t Anew = cw.A0 ^ __builtin_amdgcn_perm(dhi, dlo, 0x05040100u);
+        const uint32_t Bnew = B0 ^ __builtin_amdgcn_perm(dhi, dlo, 0x07060302u);
         st[oA0 + (uint32_t)Y * W + j] = Anew;
-        uint32_t *x = xch + buf * blockDim.x;
+        uint32_t *x = xch + bb * blockDim.x;
         x[threadIdx.x] = Bnew;
         __syncthreads();
         const uint32_t nb = x[rr * W + j_next];
         const uint32_t word = shb ? __builtin_amdgcn_alignbit(nb, Bnew, 32u - 2u * (uint32_t)shb) : nb;
         st[oB0 + (uint32_t)Yb * W + jw_out] = word;
+    };
+
+    // Each group's words are fetched before the previous group is computed.
+    // Every word read is either never written in this phase or written only
+    // by this block in the iteration that owns it, after its read.
+    int g = blockIdx.x;
+    PairWords cur{};
+    u32x4 pre[4];
+    if (Stage) {
+        constexpr int kTot = kLdsTabUnits, kK = 8;
+        const int bd = rows_per_block * W;  // the block size of every launch of this form
+        uint2 sv[kK];
+        int si[kK];
+#pragma unroll
+        for (int k = 0; k < kK; ++k) {
+            si[k] = min((int)threadIdx.x + k * bd, kTot);
+            sv[k] = table_unit(a, min(si[k], kTot - 1));
+        }
+        // unconditional (clamped) and kept after the table loads, so that
+        // the LDS writes below wait for the table loads only; the loop skips
+        // a block without a group.  The first group's draws are computed
+        // while both are in flight.
+        __builtin_amdgcn_sched_barrier(0);
+        const int g0 = min(g, n_groups - 1);
+        cur = load_words(g0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pre[k] = call_of(g0, 2 * k);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < kK; ++k) s_tabs[si[k]] = sv[k];
+        for (int i = (int)threadIdx.x + kK * bd; i < kTot; i += bd) s_tabs[i] = table_unit(a, i);
+        __syncthreads();
+    } else if (g < n_groups) {
+        cur = load_words(g);
+    }
+    int buf = 0;
+    if (Stage && g < n_groups) {  // the first group, with its draws already made
+        const int gn = g + gridDim.x;
+        PairWords nxt{};
+        auto prefetch = [&]() {
+            if (gn < n_groups) nxt = load_words(gn);
+        };
+        group(std::true_type{}, cur, g, buf, pre, prefetch);
+        cur = nxt;
+        g = gn;
+        buf = 1;
+    }
+    for (; g < n_groups; g += gridDim.x, buf ^= 1) {
+        const int gn = g + gridDim.x;
+        PairWords nxt{};
+        auto prefetch = [&]() {
+            if (gn < n_groups) nxt = load_words(gn);
+        };
+        group(std::false_type{}, cur, g, buf, pre, prefetch);
         cur = nxt;
     }
     __syncthreads();  // the exchange buffer is reused by the next phase
@@ -225,12 +303,10 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
 template <int MinWaves>
 __global__ void __launch_bounds__(1024, MinWaves) k_phase_2bit(PhaseArgs a, int rows_per_block)
 {
-    __shared__ uint2 s_tab[kDevTabEntries];
-    __shared__ uint2 s_trans[kTransEntries];
+    __shared__ __align__(16) uint2 s_tabs[kLdsTabUnits + 1];
     extern __shared__ uint32_t xch[];  // 2 x blockDim (double buffered)
-    stage_tables(s_tab, s_trans, a.dev_tab, a.trans);
     int tr[3] = {0, 0, 0};
-    phase_2bit(a, rows_per_block, s_tab, s_trans, xch, tr);
+    phase_2bit<true>(a, rows_per_block, s_tabs, xch, tr);
     block_reduce_add<3>(tr, a.track + 3 * (size_t)blockIdx.x);
 }
 
@@ -267,10 +343,10 @@ template <int MinWaves>
 __global__ void __launch_bounds__(1024, MinWaves) k_sweeps_2bit(PhaseArgs a, int rows_per_block, uint32_t sweeps,
                                                                 unsigned *counter, unsigned *err)
 {
-    __shared__ uint2 s_tab[kDevTabEntries];
-    __shared__ uint2 s_trans[kTransEntries];
+    __shared__ __align__(16) uint2 s_tabs[kLdsTabUnits + 1];
     extern __shared__ uint32_t xch[];
-    stage_tables(s_tab, s_trans, a.dev_tab, a.trans);
+    for (int i = threadIdx.x; i < kLdsTabUnits; i += blockDim.x) s_tabs[i] = table_unit(a, i);
+    __syncthreads();
     int tr[3] = {0, 0, 0};
     const uint64_t s0 = ((uint64_t)a.s_hi << 32) | a.s_lo;
     unsigned arrivals = 0;
@@ -286,7 +362,7 @@ __global__ void __launch_bounds__(1024, MinWaves) k_sweeps_2bit(PhaseArgs a, int
             b.p = p;
             b.m = mm[p];
             b.k = kk[p];
-            phase_2bit(b, rows_per_block, s_tab, s_trans, xch, tr);
+            phase_2bit<false>(b, rows_per_block, s_tabs, xch, tr);
             arrivals += gridDim.x;
             grid_barrier(counter, arrivals, err);
         }

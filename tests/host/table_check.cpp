@@ -3,7 +3,8 @@
 // launchers, then for every pair state, every choice j and every
 // neighbourhood of the two sites (4^8 code combinations):
 //   - the transition entry's new state is the j-th configuration of the
-//     same-charge set as the oracle lists it (section 3.1);
+//     same-charge set as the oracle lists it (section 3.1), and the delta
+//     entry holds the same coefficients with the XOR of old and new codes;
 //   - dot4(coef, packed sums) + C lands inside the device table, on an entry
 //     whose packed triple is the move's (nD, nV, nJ) computed here from the
 //     energy of eq. (3), and whose threshold equals the oracle's threshold.
@@ -44,10 +45,10 @@ int main()
     const double params[][4] = {{0.25, 0.5, 1.0, 1.2}, {-0.7, 0.3, -1.0, 0.4}, {1e6, 0.5, 1.0, 0.3}};
     long checks = 0;
     for (const auto &pr : params) {
-        std::vector<uint32_t> tab, dev, trans;
+        std::vector<uint32_t> tab, dev, trans, trans_d;
         build_threshold_table(pr[0], pr[1], pr[2], pr[3], tab);
         build_device_table(tab, dev);
-        build_transition_table(trans);
+        build_transition_table(trans, trans_d);
         for (int nD = -2; nD <= 2; ++nD)
             for (int nV = -16; nV <= 16; ++nV)
                 for (int nJ = -16; nJ <= 16; ++nJ)
@@ -64,6 +65,16 @@ int main()
                 int want[2] = {ca, cb};
                 if (kq > 1 && orc_pair_config(q, j, want) != 0) { printf("FAIL set\n"); return 1; }
                 if (a1 != want[0] || b1 != want[1]) { printf("FAIL new state st=%d j=%d\n", st, j); return 1; }
+                // delta form: same coefficients and offset; every field of the
+                // low half holds code_a's change, every field of the high half
+                // code_b's
+                const uint32_t *d = &trans_d[4 * (st * 6 + j)];
+                if (d[0] != coef || d[1] != (meta & 0xFFFFu) || d[3] != 0u) { printf("FAIL delta words st=%d j=%d\n", st, j); return 1; }
+                for (int f = 0; f < 16; ++f)
+                    if (((d[2] >> (2 * f)) & 3u) != (uint32_t)(f < 8 ? (a1 ^ ca) : (b1 ^ cb))) {
+                        printf("FAIL delta field st=%d j=%d f=%d\n", st, j, f);
+                        return 1;
+                    }
                 for (int nb = 0; nb < 65536; ++nb) {
                     int sSa = 0, sGa = 0, sSb = 0, sGb = 0;
                     for (int k = 0; k < 4; ++k) {
