@@ -18,7 +18,6 @@
 #include <stdint.h>
 
 #include <algorithm>
-#include <type_traits>
 
 #include "device_common.h"
 
@@ -181,13 +180,8 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
         const uint32_t call0 = (uint32_t)row_of(gg) * (uint32_t)(Lq >> 1) + 8u * (uint32_t)j;
         return philox4x32_10(a.s_lo, (uint32_t)p, call0 + (uint32_t)c, a.s_hi, a.key0, a.key1);
     };
-    // Updates the 16 pairs of group gg from its words cw.  Pre: the draws of
-    // the even calls (used first) are given in pre[] (computed while the
-    // group's words were in flight); otherwise each call is made where its
-    // pairs need it.
-    auto group = [&](auto pre_tag, const PairWords &cw, int gg, int bb, const u32x4 (&pre)[4], auto &&prefetch) {
-        constexpr bool kPre = decltype(pre_tag)::value;
-        if (!kPre) prefetch();
+    // Updates the 16 pairs of group gg from its words cw.
+    auto group = [&](const PairWords &cw, int gg, int bb) {
         const int Y = row_of(gg), Yb = brow_of(Y);
         const uint32_t B0 = __builtin_amdgcn_alignbit(cw.B0hi, cw.B0lo, fB);
         const SideSums sa = side_sums(__builtin_amdgcn_alignbit(cw.ALhi, cw.ALlo, fAL),
@@ -203,9 +197,6 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
         // and 3; handling them in that order keeps 8 packed words live.
         uint32_t dlo = 0u, dhi = 0u, packed = 0u;  // code changes of pairs 0-7 and 8-15
         const uint32_t kq2w = word_kq2(cw.A0, B0);
-        // with the draws held in registers, the next group's words are
-        // fetched once this group's neighbour words are consumed
-        if (kPre) prefetch();
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             uint32_t ge[4], go[4];
@@ -217,7 +208,7 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int c = 2 * k + half;
-                const u32x4 w = (kPre && half == 0) ? pre[k] : call_of(gg, c);
+                const u32x4 w = call_of(gg, c);
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int t = 2 * c + h;
@@ -248,7 +239,6 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
     // by this block in the iteration that owns it, after its read.
     int g = blockIdx.x;
     PairWords cur{};
-    u32x4 pre[4];
     if (Stage) {
         constexpr int kTot = kLdsTabUnits, kK = 8;
         const int bd = rows_per_block * W;  // the block size of every launch of this form
@@ -261,14 +251,9 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
         }
         // unconditional (clamped) and kept after the table loads, so that
         // the LDS writes below wait for the table loads only; the loop skips
-        // a block without a group.  The first group's draws are computed
-        // while both are in flight.
+        // a block without a group
         __builtin_amdgcn_sched_barrier(0);
-        const int g0 = min(g, n_groups - 1);
-        cur = load_words(g0);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) pre[k] = call_of(g0, 2 * k);
-        __builtin_amdgcn_sched_barrier(0);
+        cur = load_words(min(g, n_groups - 1));
 #pragma unroll
         for (int k = 0; k < kK; ++k) s_tabs[si[k]] = sv[k];
         for (int i = (int)threadIdx.x + kK * bd; i < kTot; i += bd) s_tabs[i] = table_unit(a, i);
@@ -277,24 +262,11 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
         cur = load_words(g);
     }
     int buf = 0;
-    if (Stage && g < n_groups) {  // the first group, with its draws already made
-        const int gn = g + gridDim.x;
-        PairWords nxt{};
-        auto prefetch = [&]() {
-            if (gn < n_groups) nxt = load_words(gn);
-        };
-        group(std::true_type{}, cur, g, buf, pre, prefetch);
-        cur = nxt;
-        g = gn;
-        buf = 1;
-    }
     for (; g < n_groups; g += gridDim.x, buf ^= 1) {
         const int gn = g + gridDim.x;
-        PairWords nxt{};
-        auto prefetch = [&]() {
-            if (gn < n_groups) nxt = load_words(gn);
-        };
-        group(std::false_type{}, cur, g, buf, pre, prefetch);
+        PairWords nxt;  // read only when loaded
+        if (gn < n_groups) nxt = load_words(gn);
+        group(cur, g, buf);
         cur = nxt;
     }
     __syncthreads();  // the exchange buffer is reused by the next phase
