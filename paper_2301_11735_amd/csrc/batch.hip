@@ -188,7 +188,7 @@ __device__ __forceinline__ uint32_t lane_xor(uint32_t v)
 
 template <int Q, bool Barrier>
 __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uint32_t task, const uint2 *s_tab,
-                                          const uint2 *s_trans, int (&tr)[3])
+                                          const uint4 *s_transd, int (&tr)[3])
 {
     constexpr int LOGQ = Q == 1 ? 0 : Q == 2 ? 1 : Q == 4 ? 2 : 3;
     const uint32_t wi = task >> LOGQ;
@@ -254,19 +254,18 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
     }
 
     const uint32_t call0 = (uint32_t)Y * (uint32_t)(Lq >> 1) + 8u * (uint32_t)j;
-    uint32_t dA = 0u, dB = 0u, packed = 0u;
+    // code changes of pairs 0-7 (dlo) and 8-15 (dhi): site a's in the low
+    // half, site b's in the high half
+    uint32_t dlo = 0u, dhi = 0u, packed = 0u;
     const uint32_t kq2w = word_kq2(A0, B0);
-    auto do_call = [&](int c, uint32_t be, uint32_t bo) {
+    auto do_call = [&](int c, uint32_t be, uint32_t bo, uint32_t &dacc) {
         const u32x4 w = philox4x32_10(f.s_lo, (uint32_t)f.p, call0 + (uint32_t)c, f.s_hi, f.key0, f.key1);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int t = 2 * c + h;
             const uint32_t s0 = ((A0 >> (2 * t)) & 3u) | (((B0 >> (2 * t)) & 3u) << 2);
-            const uint32_t ns = pair_step_k2(s0, (kq2w >> (2 * t)) & 3u, h ? bo : be, h ? w.z : w.x, h ? w.w : w.y,
-                                             s_trans, s_tab, packed);
-            const uint32_t dd = ns ^ s0;
-            dA |= (dd & 3u) << (2 * t);
-            dB |= (dd >> 2) << (2 * t);
+            pair_step_delta(s0, (kq2w >> (2 * t)) & 3u, h ? bo : be, h ? w.z : w.x, h ? w.w : w.y, s_transd, s_tab,
+                            0x00030003u << (2 * (t & 7)), packed, dacc);
         }
     };
     if constexpr (Q <= 2) {
@@ -280,8 +279,11 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
             transpose4((sa.OS >> sh) & kM0F, (sb.OS >> sh) & kM0F, (sa.OG >> sh) & kM0F, (sb.OG >> sh) & kM0F,
                        go[0], go[1], go[2], go[3]);
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                do_call(2 * kk + half, ge[kk], go[kk]);
+            for (int kk = 0; kk < 4; ++kk) {  // pairs 4kk .. 4kk+3
+                if (kk < 2)
+                    do_call(2 * kk + half, ge[kk], go[kk], dlo);
+                else
+                    do_call(2 * kk + half, ge[kk], go[kk], dhi);
                 if (Barrier) __builtin_amdgcn_sched_barrier(0);
             }
         }
@@ -291,14 +293,21 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
         const uint32_t rEG0 = (sa.EG >> sh) & kM0F, rEG1 = (sb.EG >> sh) & kM0F;
         const uint32_t rOS0 = (sa.OS >> sh) & kM0F, rOS1 = (sb.OS >> sh) & kM0F;
         const uint32_t rOG0 = (sa.OG >> sh) & kM0F, rOG1 = (sb.OG >> sh) & kM0F;
+        uint32_t dx = 0u;  // Q = 8: pairs 4kk .. 4kk+3 of the one call, kk = q >> 1
 #pragma unroll
-        for (int i = 0; i < 8 / Q; ++i) {
+        for (int i = 0; i < 8 / Q; ++i) {  // Q = 4: i = 0 covers pairs 0-7, i = 1 pairs 8-15
             const uint32_t kk = (uint32_t)(q >> 1) + 2u * (uint32_t)i;
             const uint32_t sel = kk | ((4u + kk) << 8) | 0x0C0C0000u;
             do_call(2 * (int)kk + half, gather_byte(rES0, rES1, rEG0, rEG1, sel),
-                    gather_byte(rOS0, rOS1, rOG0, rOG1, sel));
+                    gather_byte(rOS0, rOS1, rOG0, rOG1, sel), Q == 8 ? dx : (i == 0 ? dlo : dhi));
+        }
+        if (Q == 8) {
+            dlo = (q >> 1) < 2 ? dx : 0u;
+            dhi = (q >> 1) < 2 ? 0u : dx;
         }
     }
+    const uint32_t dA = __builtin_amdgcn_perm(dhi, dlo, 0x05040100u);
+    const uint32_t dB = __builtin_amdgcn_perm(dhi, dlo, 0x07060302u);
     unpack_tracker(packed, tr);
     if (Q == 1) {
         if (dA) lat[f.oA0 + ro + j] = A0 ^ dA;
@@ -317,7 +326,7 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
 
 template <int Q, bool Barrier>
 __device__ __forceinline__ void word_sweeps(uint32_t *lat, uint32_t *sched, const LatDesc &d, uint32_t my_sweeps,
-                                            const uint2 *s_tab, const uint2 *s_trans, int (&tr)[3])
+                                            const uint2 *s_tab, const uint4 *s_transd, int (&tr)[3])
 {
     WordPhase f;
     f.W = d.L >> 6;
@@ -360,7 +369,8 @@ __device__ __forceinline__ void word_sweeps(uint32_t *lat, uint32_t *sched, cons
                 o[2] = w.z;
                 o[3] = w.w;
             }
-            for (uint32_t t = threadIdx.x; t < tasks; t += blockDim.x) word_task<Q, Barrier>(lat, f, t, s_tab, s_trans, tr);
+            for (uint32_t t = threadIdx.x; t < tasks; t += blockDim.x)
+                word_task<Q, Barrier>(lat, f, t, s_tab, s_transd, tr);
             __syncthreads();
         }
     }
@@ -373,7 +383,7 @@ __global__ void __launch_bounds__(MaxThreads) k_sweep_lds_w(BatchArgs args)
 {
     constexpr bool kBarrier = MaxThreads > 512;
     __shared__ uint2 s_tab[kDevTabEntries];
-    __shared__ uint2 s_trans[kTransEntries];
+    __shared__ uint4 s_transd[kTransEntries];
     __shared__ uint32_t sched[24];
     extern __shared__ uint32_t lat[];
     uint8_t *scr = args.scratch[blockIdx.x];
@@ -394,7 +404,13 @@ __global__ void __launch_bounds__(MaxThreads) k_sweep_lds_w(BatchArgs args)
     g.Wp = d.L >> 6;
     g.csz = (uint32_t)g.H * g.Wp;
     stage_lattice(lat, d, g);
-    stage_tables(s_tab, s_trans, (const uint2 *)(scr + kScrDevTab), (const uint2 *)(scr + kScrTrans));
+    {
+        const uint2 *g_tab = (const uint2 *)(scr + kScrDevTab);
+        const uint4 *g_transd = (const uint4 *)(scr + kScrTransD);
+        for (int i = threadIdx.x; i < kDevTabEntries; i += blockDim.x) s_tab[i] = g_tab[i];
+        for (int i = threadIdx.x; i < kTransEntries; i += blockDim.x) s_transd[i] = g_transd[i];
+        __syncthreads();
+    }
 
     // threads per a-word: the largest Q <= 8 with Q * (a-words) <= block size
     const uint32_t words = g.csz;
@@ -402,10 +418,10 @@ __global__ void __launch_bounds__(MaxThreads) k_sweep_lds_w(BatchArgs args)
     while (Q < 8 && words * (uint32_t)(2 * Q) <= blockDim.x) Q *= 2;
     int tr[3] = {0, 0, 0};
     switch (Q) {
-    case 1: word_sweeps<1, kBarrier>(lat, sched, d, my_sweeps, s_tab, s_trans, tr); break;
-    case 2: word_sweeps<2, kBarrier>(lat, sched, d, my_sweeps, s_tab, s_trans, tr); break;
-    case 4: word_sweeps<4, kBarrier>(lat, sched, d, my_sweeps, s_tab, s_trans, tr); break;
-    default: word_sweeps<8, kBarrier>(lat, sched, d, my_sweeps, s_tab, s_trans, tr); break;
+    case 1: word_sweeps<1, kBarrier>(lat, sched, d, my_sweeps, s_tab, s_transd, tr); break;
+    case 2: word_sweeps<2, kBarrier>(lat, sched, d, my_sweeps, s_tab, s_transd, tr); break;
+    case 4: word_sweeps<4, kBarrier>(lat, sched, d, my_sweeps, s_tab, s_transd, tr); break;
+    default: word_sweeps<8, kBarrier>(lat, sched, d, my_sweeps, s_tab, s_transd, tr); break;
     }
     unstage_lattice(lat, d, g);
     if (threadIdx.x == 0) ((LatDesc *)(scr + kScrDesc))->next_sweep = d.next_sweep + my_sweeps;
