@@ -213,6 +213,18 @@ __device__ __forceinline__ void device_schedule(int L, uint32_t k0, uint32_t k1,
     }
 }
 
+// Word i of an array below 4 GiB (every lattice state is): a 32-bit byte
+// offset from the base, so that a uniform base stays in scalar registers and
+// no 64-bit address is formed per access.
+__device__ __forceinline__ uint32_t word_at(const uint32_t *base, uint32_t i)
+{
+    return *(const uint32_t *)((const uint8_t *)base + (i << 2));
+}
+__device__ __forceinline__ void word_put(uint32_t *base, uint32_t i, uint32_t v)
+{
+    *(uint32_t *)((uint8_t *)base + (i << 2)) = v;
+}
+
 // The two words of the class row at word offset `row` that hold the 16 sites
 // starting at class position xs (periodic); alignbit(hi, lo, 2 (xs mod 16))
 // then gives the 16 sites (a shift of 0 gives lo).
@@ -220,8 +232,8 @@ __device__ __forceinline__ void load_pair(const uint32_t *__restrict__ st, uint3
                                           uint32_t &hi)
 {
     const int jw = xs >> 4;
-    lo = st[row + (uint32_t)jw];
-    hi = st[row + (uint32_t)(jw + 1 == W ? 0 : jw + 1)];
+    lo = word_at(st, row + (uint32_t)jw);
+    hi = word_at(st, row + (uint32_t)(jw + 1 == W ? 0 : jw + 1));
 }
 
 // 16 sites of the class row at word offset `row` of `st`, starting at class
@@ -229,8 +241,8 @@ __device__ __forceinline__ void load_pair(const uint32_t *__restrict__ st, uint3
 __device__ __forceinline__ uint32_t load16(const uint32_t *__restrict__ st, uint32_t row, int W, int xs)
 {
     const int jw = xs >> 4, sh = xs & 15;
-    const uint32_t w0 = st[row + (uint32_t)jw];
-    const uint32_t w1 = st[row + (uint32_t)(jw + 1 == W ? 0 : jw + 1)];
+    const uint32_t w0 = word_at(st, row + (uint32_t)jw);
+    const uint32_t w1 = word_at(st, row + (uint32_t)(jw + 1 == W ? 0 : jw + 1));
     return sh ? __builtin_amdgcn_alignbit(w1, w0, 2u * (uint32_t)sh) : w0;
 }
 

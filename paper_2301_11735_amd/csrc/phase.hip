@@ -159,9 +159,9 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
         const uint32_t roU = (uint32_t)(Y == 0 ? H - 1 : Y - 1) * W;
         const uint32_t robD = (uint32_t)(Yb + 1 == H ? 0 : Yb + 1) * W;
         PairWords w;
-        w.A0 = st[oA0 + ro + j];
-        w.AU = st[oAV + roU + j];
-        w.AD = st[oAV + ro + j];
+        w.A0 = word_at(st, oA0 + ro + j);
+        w.AU = word_at(st, oAV + roU + j);
+        w.AD = word_at(st, oAV + ro + j);
         load_pair(st, oAL + ro, W, xAL, w.ALlo, w.ALhi);
         load_pair(st, oAR + ro, W, xAR, w.ARlo, w.ARhi);
         load_pair(st, oB0 + rob, W, Xb, w.B0lo, w.B0hi);
@@ -225,13 +225,13 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
         unpack_tracker(packed, tr);
         const uint32_t Anew = cw.A0 ^ __builtin_amdgcn_perm(dhi, dlo, 0x05040100u);
         const uint32_t Bnew = B0 ^ __builtin_amdgcn_perm(dhi, dlo, 0x07060302u);
-        st[oA0 + (uint32_t)Y * W + j] = Anew;
+        word_put(st, oA0 + (uint32_t)Y * W + j, Anew);
         uint32_t *x = xch + bb * blockDim.x;
         x[threadIdx.x] = Bnew;
         __syncthreads();
         const uint32_t nb = x[rr * W + j_next];
         const uint32_t word = shb ? __builtin_amdgcn_alignbit(nb, Bnew, 32u - 2u * (uint32_t)shb) : nb;
-        st[oB0 + (uint32_t)Yb * W + jw_out] = word;
+        word_put(st, oB0 + (uint32_t)Yb * W + jw_out, word);
     };
 
     // Each group's words are fetched before the previous group is computed.
