@@ -265,14 +265,32 @@ __device__ __forceinline__ void side_add(SideSums &s, uint32_t w)
     s.OG += (vG >> 2) & kM3;
 }
 
+// The sums over all four neighbour words at once, from three indicator
+// planes per word (one bit per site, at the low bit of its field): h (a
+// charge), P (charge +1) and U (spin +1).  Per site 1+S = 2P + 1 - h and
+// 1+sigma = 2U + h, so over the four neighbours
+//   4 + sum S = 4 + 2 sum P - sum h,   4 + sum sigma = 2 sum U + sum h.
+// Two words' planes add without carry in 2-bit fields (at most 2); the two
+// pair sums are then split into even and odd sites and added in nibbles (at
+// most 4), and the nibble combinations stay within 0..8.
 __device__ __forceinline__ SideSums side_sums(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3)
 {
-    SideSums s{0u, 0u, 0u, 0u};
-    side_add(s, w0);
-    side_add(s, w1);
-    side_add(s, w2);
-    side_add(s, w3);
-    return s;
+    uint32_t h[4], P[4], U[4];
+    const uint32_t w[4] = {w0, w1, w2, w3};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        h[i] = (w[i] >> 1) & kM5;
+        P[i] = h[i] & ~w[i];
+        U[i] = ~(h[i] | w[i]) & kM5;
+    }
+    const uint32_t h01 = h[0] + h[1], h23 = h[2] + h[3];
+    const uint32_t P01 = P[0] + P[1], P23 = P[2] + P[3];
+    const uint32_t U01 = U[0] + U[1], U23 = U[2] + U[3];
+    const uint32_t hE = (h01 & kM3) + (h23 & kM3), hO = ((h01 >> 2) & kM3) + ((h23 >> 2) & kM3);
+    const uint32_t PE = (P01 & kM3) + (P23 & kM3), PO = ((P01 >> 2) & kM3) + ((P23 >> 2) & kM3);
+    const uint32_t UE = (U01 & kM3) + (U23 & kM3), UO = ((U01 >> 2) & kM3) + ((U23 >> 2) & kM3);
+    constexpr uint32_t kFour = 0x44444444u;  // 4 in every nibble
+    return SideSums{kFour + 2u * PE - hE, kFour + 2u * PO - hO, 2u * UE + hE, 2u * UO + hO};
 }
 
 // 4x4 byte transpose: out[k] = (r0.byte k, r1.byte k, r2.byte k, r3.byte k).
