@@ -177,6 +177,7 @@ def parse():
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-maps", action="store_true")
+    ap.add_argument("--no-penalty", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="0 skips the served run")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only copy a device buffer of this many MiB 3 times (HBM counter calibration) and exit")
@@ -312,6 +313,26 @@ def map_run(torch, lat, n_maps: int = 100) -> dict:
     }
 
 
+def penalty_run(torch, lat, L: int = 4096, sweeps: int = 20) -> dict:
+    """Penalty mode (section 2.2's prior method: single-site checkerboard
+    Metropolis, mu adjusted after every sweep) on one int8 lattice with the
+    large lattice's parameters.  Wall-clock rate, including the per-sweep
+    host rebuild of the mu table and the charge read-back."""
+    s = workloads.LARGE
+    g = lat.Lattice(L, s.n, s.Delta, s.V, s.J, s.T, s.seed, encoding=lat.ENC_INT8)
+    mu, _, _ = g.mu_sweeps(0, 2, 0.5, 0.0)  # warm-up (not counted)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.mu_sweeps(2, sweeps, 0.5, mu)
+    dt = time.perf_counter() - t0
+    g.destroy()
+    return {
+        "workload": f"one int8 lattice L={L}, J=1 V=0.5 Delta=0.25 T=1.2 n=0.1 seed 3, kappa 0.5, {sweeps} sweeps",
+        "site_updates_per_s": L * L * sweeps / dt,
+        "ms_per_sweep": 1e3 * dt / sweeps,
+    }
+
+
 def served_run(seconds: float) -> dict:
     from paper_2301_11735_amd import serve as serve_mod
 
@@ -438,6 +459,8 @@ def main():
         line["batched"] = batched_run(torch, lat)
     if not args.no_maps:
         line["map_mode"] = map_run(torch, lat)
+    if not args.no_penalty:
+        line["penalty_mode"] = penalty_run(torch, lat)
     if args.serve_seconds > 0:
         line["served"] = served_run(args.serve_seconds)
     if not args.no_cpu_baseline:
