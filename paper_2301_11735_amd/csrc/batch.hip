@@ -186,9 +186,36 @@ __device__ __forceinline__ uint32_t lane_xor(uint32_t v)
         return (uint32_t)__shfl_xor((int)v, XOR, 64);
 }
 
-template <int Q, bool Barrier>
+// Philox calls a task makes: all 8 of its word (Q = 1) or 8/Q of them.  The
+// i-th is call_of_task(q, i), in the order word_task uses them.
+template <int Q>
+constexpr int kTaskCalls = Q == 1 ? 8 : 8 / Q;
+template <int Q>
+__device__ __forceinline__ int call_of_task(int q, int i)
+{
+    if constexpr (Q == 1) return i < 4 ? 2 * i : 2 * (i - 4) + 1;
+    else if constexpr (Q == 2) return 2 * i + q;
+    else return 2 * ((q >> 1) + 2 * i) + (q & 1);
+}
+
+// First counter word of a task's word (its a-word's first Philox call): the
+// same in every phase, since each phase's a-class has the same shape.
+template <int Q>
+__device__ __forceinline__ uint32_t task_call0(const WordPhase &f, uint32_t task)
+{
+    constexpr int LOGQ = Q == 1 ? 0 : Q == 2 ? 1 : Q == 4 ? 2 : 3;
+    const uint32_t wi = task >> LOGQ;
+    const int Y = f.W == 1 ? (int)wi : (int)__umulhi(wi, f.magicW), j = (int)wi - Y * f.W;
+    return (uint32_t)Y * (uint32_t)(f.Lq >> 1) + 8u * (uint32_t)j;
+}
+
+// Pipe: the task's draws for this phase are given in pre[], and those of the
+// next phase (sweep ns, phase np) are computed here, between the phase's
+// dependent LDS lookups, and returned in pre[].
+template <int Q, bool Barrier, bool Pipe = false>
 __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uint32_t task, const uint2 *s_tab,
-                                          const uint4 *s_transd, int (&tr)[3])
+                                          const uint4 *s_transd, int (&tr)[3], u32x4 *pre = nullptr,
+                                          uint64_t ns = 0, int np = 0)
 {
     constexpr int LOGQ = Q == 1 ? 0 : Q == 2 ? 1 : Q == 4 ? 2 : 3;
     const uint32_t wi = task >> LOGQ;
@@ -258,8 +285,16 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
     // half, site b's in the high half
     uint32_t dlo = 0u, dhi = 0u, packed = 0u;
     const uint32_t kq2w = word_kq2(A0, B0);
-    auto do_call = [&](int c, uint32_t be, uint32_t bo, uint32_t &dacc) {
-        const u32x4 w = philox4x32_10(f.s_lo, (uint32_t)f.p, call0 + (uint32_t)c, f.s_hi, f.key0, f.key1);
+    u32x4 nxt[kTaskCalls<Q>];
+    if constexpr (Pipe) {
+#pragma unroll
+        for (int i = 0; i < kTaskCalls<Q>; ++i)
+            nxt[i] = philox4x32_10((uint32_t)ns, (uint32_t)np, call0 + (uint32_t)call_of_task<Q>(q, i),
+                                   (uint32_t)(ns >> 32), f.key0, f.key1);
+    }
+    auto do_call = [&](int i, int c, uint32_t be, uint32_t bo, uint32_t &dacc) {
+        const u32x4 w =
+            Pipe ? pre[i] : philox4x32_10(f.s_lo, (uint32_t)f.p, call0 + (uint32_t)c, f.s_hi, f.key0, f.key1);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int t = 2 * c + h;
@@ -280,10 +315,11 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
                        go[0], go[1], go[2], go[3]);
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {  // pairs 4kk .. 4kk+3
+                const int slot = Q == 1 ? 4 * hh + kk : kk;
                 if (kk < 2)
-                    do_call(2 * kk + half, ge[kk], go[kk], dlo);
+                    do_call(slot, 2 * kk + half, ge[kk], go[kk], dlo);
                 else
-                    do_call(2 * kk + half, ge[kk], go[kk], dhi);
+                    do_call(slot, 2 * kk + half, ge[kk], go[kk], dhi);
                 if (Barrier) __builtin_amdgcn_sched_barrier(0);
             }
         }
@@ -298,7 +334,7 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
         for (int i = 0; i < 8 / Q; ++i) {  // Q = 4: i = 0 covers pairs 0-7, i = 1 pairs 8-15
             const uint32_t kk = (uint32_t)(q >> 1) + 2u * (uint32_t)i;
             const uint32_t sel = kk | ((4u + kk) << 8) | 0x0C0C0000u;
-            do_call(2 * (int)kk + half, gather_byte(rES0, rES1, rEG0, rEG1, sel),
+            do_call(i, 2 * (int)kk + half, gather_byte(rES0, rES1, rEG0, rEG1, sel),
                     gather_byte(rOS0, rOS1, rOG0, rOG1, sel), Q == 8 ? dx : (i == 0 ? dlo : dhi));
         }
         if (Q == 8) {
@@ -308,6 +344,10 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
     }
     const uint32_t dA = __builtin_amdgcn_perm(dhi, dlo, 0x05040100u);
     const uint32_t dB = __builtin_amdgcn_perm(dhi, dlo, 0x07060302u);
+    if constexpr (Pipe) {
+#pragma unroll
+        for (int i = 0; i < kTaskCalls<Q>; ++i) pre[i] = nxt[i];
+    }
     unpack_tracker(packed, tr);
     if (Q == 1) {
         if (dA) lat[f.oA0 + ro + j] = A0 ^ dA;
@@ -337,6 +377,19 @@ __device__ __forceinline__ void word_sweeps(uint32_t *lat, uint32_t *sched, cons
     f.key1 = d.key1;
     const uint32_t csz = (uint32_t)f.H * (uint32_t)f.W;
     const uint32_t tasks = csz * (uint32_t)Q;
+    // At most one task per thread (and Q >= 2, so that the held draws stay
+    // few): each phase makes the next phase's draws of the thread's task
+    // while its own table lookups are in flight.
+    const bool pipe = Q >= 2 && tasks <= blockDim.x;
+    u32x4 pre[kTaskCalls<Q>];
+    if (pipe && threadIdx.x < tasks && my_sweeps > 0) {
+        const uint32_t c0 = task_call0<Q>(f, threadIdx.x);
+        const int q = (int)(threadIdx.x & (uint32_t)(Q - 1));
+#pragma unroll
+        for (int i = 0; i < kTaskCalls<Q>; ++i)
+            pre[i] = philox4x32_10((uint32_t)d.next_sweep, 0u, c0 + (uint32_t)call_of_task<Q>(q, i),
+                                   (uint32_t)(d.next_sweep >> 32), d.key0, d.key1);
+    }
     for (uint32_t i = 0; i < my_sweeps; ++i) {
         const uint64_t s = d.next_sweep + i;
         const uint32_t *Wd = sched + 12u * (i & 1u);
@@ -369,8 +422,14 @@ __device__ __forceinline__ void word_sweeps(uint32_t *lat, uint32_t *sched, cons
                 o[2] = w.z;
                 o[3] = w.w;
             }
-            for (uint32_t t = threadIdx.x; t < tasks; t += blockDim.x)
-                word_task<Q, Barrier>(lat, f, t, s_tab, s_transd, tr);
+            if (pipe) {
+                if (threadIdx.x < tasks)
+                    word_task<Q, Barrier, true>(lat, f, threadIdx.x, s_tab, s_transd, tr, pre, p < 3 ? s : s + 1,
+                                                p < 3 ? p + 1 : 0);
+            } else {
+                for (uint32_t t = threadIdx.x; t < tasks; t += blockDim.x)
+                    word_task<Q, Barrier>(lat, f, t, s_tab, s_transd, tr);
+            }
             __syncthreads();
         }
     }
