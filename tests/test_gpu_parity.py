@@ -189,6 +189,16 @@ def test_phase_kernel_path_matches_oracle(spec, monkeypatch):
     _run_parity(spec, [1, 3, 10])
 
 
+@pytest.mark.parametrize("rows,bpc", [(1, 1), (2, 4), (32, 1), (8, 2)])
+def test_phase_kernel_launch_shapes_match_oracle(rows, bpc, monkeypatch):
+    """The 2-bit phase kernel under other launch shapes (rows of the a-class
+    per block, blocks per compute unit) than the default: the same chain."""
+    monkeypatch.setenv("LATTICE_FORCE_PHASE_KERNELS", "1")
+    monkeypatch.setenv("LATTICE_2BIT_ROWS", str(rows))
+    monkeypatch.setenv("LATTICE_2BIT_BLOCKS_PER_CU", str(bpc))
+    _run_parity(SMALL.with_(L=256, encoding=1, T=0.8, n=-0.2, seed=66), [1, 4])
+
+
 def _make(spec):
     return lat.Lattice(spec.L, spec.n, spec.Delta, spec.V, spec.J, spec.T, spec.seed, encoding=spec.encoding,
                        n_charged=spec.n_charged)
