@@ -98,22 +98,25 @@ struct PairWords {
 
 // LDS tables of the 2-bit phase kernels, in 8-byte units: the device
 // threshold table, one pad entry, the delta transition table (16-byte
-// aligned), and one spare entry that absorbs the writes of threads past the
-// end during staging.
+// aligned), and two spare entries that absorb the writes of threads past the
+// end during staging.  Staging moves 16 bytes (two units) at a time.
 constexpr int kLdsTransD = kDevTabEntries + 1;                // 934: 16-byte aligned
 constexpr int kLdsTabUnits = kLdsTransD + 2 * kTransEntries;  // 1126
-static_assert((kLdsTransD * 8) % 16 == 0, "delta table alignment");
+constexpr int kLdsTabPairs = kLdsTabUnits / 2;                // 563
+static_assert((kLdsTransD * 8) % 16 == 0 && kLdsTabUnits % 2 == 0, "delta table alignment");
+static_assert(kScrTrans >= (size_t)kLdsTransD * 8, "the last device-table pair reads scratch, not past it");
 
-__device__ __forceinline__ uint2 table_unit(const PhaseArgs &a, int i)
+// Units 2i and 2i+1 of the LDS tables from the lattice's scratch.  The pair
+// holding the pad unit reads the scratch bytes after the device table.
+__device__ __forceinline__ uint4 table_pair(const PhaseArgs &a, int i)
 {
-    return i < kLdsTransD ? a.dev_tab[min(i, kDevTabEntries - 1)]
-                          : ((const uint2 *)a.trans_d)[i - kLdsTransD];
+    return 2 * i < kLdsTransD ? *(const uint4 *)(a.dev_tab + 2 * i) : a.trans_d[i - kLdsTransD / 2];
 }
 
 // One phase of the 2-bit lattice by this block: row groups blockIdx.x,
 // blockIdx.x + gridDim.x, ...
 //
-// s_tabs holds kLdsTabUnits + 1 entries.  Stage false: the tables are
+// s_tabs holds kLdsTabUnits + 2 entries.  Stage false: the tables are
 // already there.  Stage true: they are copied here; the table loads are
 // issued first, then the first group's words, so that the LDS writes wait
 // only for the former and the word loads overlap the staging.
@@ -240,23 +243,24 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
     int g = blockIdx.x;
     PairWords cur{};
     if (Stage) {
-        constexpr int kTot = kLdsTabUnits, kK = 8;
+        constexpr int kTot = kLdsTabPairs, kK = 2;  // two 16-byte loads a thread cover 512-thread blocks
         const int bd = rows_per_block * W;  // the block size of every launch of this form
-        uint2 sv[kK];
+        uint4 sv[kK];
         int si[kK];
 #pragma unroll
         for (int k = 0; k < kK; ++k) {
             si[k] = min((int)threadIdx.x + k * bd, kTot);
-            sv[k] = table_unit(a, min(si[k], kTot - 1));
+            sv[k] = table_pair(a, min(si[k], kTot - 1));
         }
         // unconditional (clamped) and kept after the table loads, so that
         // the LDS writes below wait for the table loads only; the loop skips
         // a block without a group
         __builtin_amdgcn_sched_barrier(0);
         cur = load_words(min(g, n_groups - 1));
+        uint4 *s_pairs = (uint4 *)s_tabs;
 #pragma unroll
-        for (int k = 0; k < kK; ++k) s_tabs[si[k]] = sv[k];
-        for (int i = (int)threadIdx.x + kK * bd; i < kTot; i += bd) s_tabs[i] = table_unit(a, i);
+        for (int k = 0; k < kK; ++k) s_pairs[si[k]] = sv[k];
+        for (int i = (int)threadIdx.x + kK * bd; i < kTot; i += bd) s_pairs[i] = table_pair(a, i);
         __syncthreads();
     } else if (g < n_groups) {
         cur = load_words(g);
@@ -275,7 +279,7 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
 template <int MinWaves>
 __global__ void __launch_bounds__(1024, MinWaves) k_phase_2bit(PhaseArgs a, int rows_per_block)
 {
-    __shared__ __align__(16) uint2 s_tabs[kLdsTabUnits + 1];
+    __shared__ __align__(16) uint2 s_tabs[kLdsTabUnits + 2];
     extern __shared__ uint32_t xch[];  // 2 x blockDim (double buffered)
     int tr[3] = {0, 0, 0};
     phase_2bit<true>(a, rows_per_block, s_tabs, xch, tr);
@@ -315,9 +319,9 @@ template <int MinWaves>
 __global__ void __launch_bounds__(1024, MinWaves) k_sweeps_2bit(PhaseArgs a, int rows_per_block, uint32_t sweeps,
                                                                 unsigned *counter, unsigned *err)
 {
-    __shared__ __align__(16) uint2 s_tabs[kLdsTabUnits + 1];
+    __shared__ __align__(16) uint2 s_tabs[kLdsTabUnits + 2];
     extern __shared__ uint32_t xch[];
-    for (int i = threadIdx.x; i < kLdsTabUnits; i += blockDim.x) s_tabs[i] = table_unit(a, i);
+    for (int i = threadIdx.x; i < kLdsTabPairs; i += blockDim.x) ((uint4 *)s_tabs)[i] = table_pair(a, i);
     __syncthreads();
     int tr[3] = {0, 0, 0};
     const uint64_t s0 = ((uint64_t)a.s_hi << 32) | a.s_lo;
