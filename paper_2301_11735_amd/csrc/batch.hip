@@ -92,7 +92,6 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(BatchArgs args)
     g.Wp = (g.Lq + 15) >> 4;
     g.csz = (uint32_t)g.H * g.Wp;
     const int L = g.L, Lq = g.Lq, H = g.H;
-    const uint32_t nwords = 8u * g.csz;
 
     stage_lattice(lat, d, g);
     __syncthreads();

@@ -43,9 +43,8 @@ __device__ __forceinline__ void site_neighbours(int L, uint32_t s, uint32_t (&nb
     nb[3] = (y == 0 ? (uint32_t)L * ((uint32_t)L - 1) : row - (uint32_t)L) + x;
 }
 
-__device__ __forceinline__ void mark(uint32_t *bitmap, uint32_t s) { bitmap[s >> 5] |= 1u << (s & 31u); }
-
-// Map m into pairs[] (a | b << 16), by wave 0 of the block.  Per round the
+// Map m into pairs[] (a | b << 16), by the calling wave (several waves of a
+// block build different maps at once, each in its own bitmap).  Per round the
 // 64 lanes compute the next 256 site draws, their neighbours and whether each
 // was already marked when the round began (one ballot per draw slot); then the
 // wave walks the draws in draw order with uniform control flow: a draw marked
