@@ -220,9 +220,6 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
                     pair_step_delta(s0, (kq2w >> (2 * t)) & 3u, h ? go[k] : ge[k], h ? w.z : w.x, h ? w.w : w.y,
                                     s_transd, s_tab, fields, packed, t < 8 ? dlo : dhi);
                 }
-                // keep the scheduler from hoisting every Philox call at once
-                // (register pressure decides how many waves fit per SIMD)
-                __builtin_amdgcn_sched_barrier(0);
             }
         }
         unpack_tracker(packed, tr);
