@@ -348,19 +348,16 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
         for (int i = 0; i < kTaskCalls<Q>; ++i) pre[i] = nxt[i];
     }
     unpack_tracker(packed, tr);
-    if (Q == 1) {
-        if (dA) lat[f.oA0 + ro + j] = A0 ^ dA;
-    } else if (dA) {
+    // unconditional (an XOR with 0 changes nothing): branches on the masks
+    // cost more than the LDS operations they would skip
+    if (Q == 1)
+        lat[f.oA0 + ro + j] = A0 ^ dA;
+    else
         atomicXor(&lat[f.oA0 + ro + j], dA);
-    }
-    if (dB) {
-        const int jb = Xb >> 4, shb = Xb & 15;
-        atomicXor(&lat[f.oB0 + rob + (uint32_t)jb], dB << (2 * shb));
-        if (shb) {
-            const uint32_t hi = dB >> (32 - 2 * shb);
-            if (hi) atomicXor(&lat[f.oB0 + rob + (uint32_t)(jb + 1 == W ? 0 : jb + 1)], hi);
-        }
-    }
+    const int jb = Xb >> 4, shb = Xb & 15;
+    atomicXor(&lat[f.oB0 + rob + (uint32_t)jb], dB << (2 * shb));
+    const uint32_t hi = shb ? dB >> (32 - 2 * shb) : 0u;
+    atomicXor(&lat[f.oB0 + rob + (uint32_t)(jb + 1 == W ? 0 : jb + 1)], hi);
 }
 
 template <int Q, bool Barrier>
