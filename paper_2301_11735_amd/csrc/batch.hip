@@ -348,16 +348,33 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
         for (int i = 0; i < kTaskCalls<Q>; ++i) pre[i] = nxt[i];
     }
     unpack_tracker(packed, tr);
-    // unconditional (an XOR with 0 changes nothing): branches on the masks
-    // cost more than the LDS operations they would skip
-    if (Q == 1)
-        lat[f.oA0 + ro + j] = A0 ^ dA;
-    else
-        atomicXor(&lat[f.oA0 + ro + j], dA);
     const int jb = Xb >> 4, shb = Xb & 15;
-    atomicXor(&lat[f.oB0 + rob + (uint32_t)jb], dB << (2 * shb));
-    const uint32_t hi = shb ? dB >> (32 - 2 * shb) : 0u;
-    atomicXor(&lat[f.oB0 + rob + (uint32_t)(jb + 1 == W ? 0 : jb + 1)], hi);
+    if constexpr (!Barrier) {
+        // unconditional (an XOR with 0 changes nothing): branches on the
+        // masks cost more than the LDS operations they would skip
+        if (Q == 1)
+            lat[f.oA0 + ro + j] = A0 ^ dA;
+        else
+            atomicXor(&lat[f.oA0 + ro + j], dA);
+        atomicXor(&lat[f.oB0 + rob + (uint32_t)jb], dB << (2 * shb));
+        const uint32_t hi = shb ? dB >> (32 - 2 * shb) : 0u;
+        atomicXor(&lat[f.oB0 + rob + (uint32_t)(jb + 1 == W ? 0 : jb + 1)], hi);
+    } else {
+        // the 1024-thread build keeps the branches: without them it needs
+        // more registers than 16 waves a compute unit leave
+        if (Q == 1) {
+            if (dA) lat[f.oA0 + ro + j] = A0 ^ dA;
+        } else if (dA) {
+            atomicXor(&lat[f.oA0 + ro + j], dA);
+        }
+        if (dB) {
+            atomicXor(&lat[f.oB0 + rob + (uint32_t)jb], dB << (2 * shb));
+            if (shb) {
+                const uint32_t hi = dB >> (32 - 2 * shb);
+                if (hi) atomicXor(&lat[f.oB0 + rob + (uint32_t)(jb + 1 == W ? 0 : jb + 1)], hi);
+            }
+        }
+    }
 }
 
 template <int Q, bool Barrier>
@@ -431,6 +448,57 @@ __device__ __forceinline__ void word_sweeps(uint32_t *lat, uint32_t *sched, cons
     }
 }
 
+// This thread's share of the 7 observable sums of a 2-bit lattice in the
+// class layout, read from st (global memory or the LDS copy).
+__device__ __forceinline__ void obs_sums_2bit(const uint32_t *st, int L, long long (&v)[7])
+{
+    const int W = L >> 6, H = L >> 1, Lq = L >> 2;
+    const uint32_t csz = (uint32_t)H * W;
+    for (uint32_t i = threadIdx.x; i < 8u * csz; i += blockDim.x) {
+        const int c = (int)(i / csz);
+        const uint32_t rem = i - (uint32_t)c * csz;
+        const int Y = (int)(rem / W), j = (int)(rem - (uint32_t)Y * W);
+        const int cx = c & 3, cy = c >> 2;
+        const uint32_t w = st[i];
+        const uint32_t wr = cx < 3 ? st[i + csz]
+                                   : load16(st, (uint32_t)(4 * cy) * csz + (uint32_t)Y * W, W,
+                                            16 * j + 1 == Lq ? 0 : 16 * j + 1);
+        const uint32_t wd = cy == 0 ? st[i + 4 * csz] : st[(uint32_t)cx * csz + (uint32_t)(Y + 1 == H ? 0 : Y + 1) * W + j];
+        const uint32_t h = (w >> 1) & kM5, l = w & kM5;
+        const int sumS = __popc(h & ~l) - __popc(h & l);
+        const int sumG = __popc((h | l) ^ kM5) - __popc(l & ~h);
+        int bSS = 0, bss = 0;
+        bond_sums(h, l, (wr >> 1) & kM5, wr & kM5, bSS, bss);
+        bond_sums(h, l, (wd >> 1) & kM5, wd & kM5, bSS, bss);
+        const int sg = ((cx + cy) & 1) ? -1 : 1;
+        v[0] += sumS;
+        v[1] += __popc(h);
+        v[2] += bSS;
+        v[3] += bss;
+        v[4] += sumG;
+        v[5] += sg * sumG;
+        v[6] += sg * sumS;
+    }
+}
+
+// This thread's share of a lattice's tracker slots (phase kernels) and, for
+// thread 0, its tracker base (single-block kernels).
+__device__ __forceinline__ void tracker_partial(const uint8_t *scr, long long (&t3)[3])
+{
+    const long long *slots = (const long long *)(scr + kScrSlots);
+    for (int i = threadIdx.x; i < kMaxSlots; i += blockDim.x) {
+        t3[0] += slots[3 * i];
+        t3[1] += slots[3 * i + 1];
+        t3[2] += slots[3 * i + 2];
+    }
+    if (threadIdx.x == 0) {
+        const long long *base = (const long long *)(scr + kScrTrackBase);
+        t3[0] += base[0];
+        t3[1] += base[1];
+        t3[2] += base[2];
+    }
+}
+
 // MaxThreads = 512 serves blocks of up to 512 threads (measured faster: the
 // compiler schedules for fewer waves per SIMD), 1024 the largest blocks.
 template <int MaxThreads>
@@ -478,6 +546,22 @@ __global__ void __launch_bounds__(MaxThreads) k_sweep_lds_w(BatchArgs args)
     case 4: word_sweeps<4, kBarrier>(lat, sched, d, my_sweeps, s_tab, s_transd, tr); break;
     default: word_sweeps<8, kBarrier>(lat, sched, d, my_sweeps, s_tab, s_transd, tr); break;
     }
+    if constexpr (MaxThreads <= 512) {
+        if (args.obs_out) {
+            // the interval's observables from the LDS copy, and the tracker
+            // total as k_obs_batch would read it after this launch: the
+            // slots, the base before this launch and this launch's own moves
+            unsigned long long *o = args.obs_out + 10 * (size_t)blockIdx.x;
+            long long t3[3] = {tr[0], tr[1], tr[2]};
+            tracker_partial(scr, t3);
+            long long v[7] = {0, 0, 0, 0, 0, 0, 0};
+            obs_sums_2bit(lat, d.L, v);
+            if (threadIdx.x < 10) o[threadIdx.x] = 0ull;
+            __syncthreads();
+            block_reduce_add<7>(v, o + 3);
+            block_reduce_add<3>(t3, o);
+        }
+    }
     unstage_lattice(lat, d, g);
     if (threadIdx.x == 0) ((LatDesc *)(scr + kScrDesc))->next_sweep = d.next_sweep + my_sweeps;
     block_reduce_add<3>(tr, (unsigned long long *)(scr + kScrTrackBase));
@@ -513,52 +597,14 @@ __global__ void __launch_bounds__(256) k_obs_batch(BatchArgs args, unsigned long
             v[6] += sg * S;
         }
     } else {
-        const uint32_t *st = (const uint32_t *)d.state;
-        const int W = L >> 6, H = L >> 1, Lq = L >> 2;
-        const uint32_t csz = (uint32_t)H * W;
-        for (uint32_t i = threadIdx.x; i < 8u * csz; i += blockDim.x) {
-            const int c = (int)(i / csz);
-            const uint32_t rem = i - (uint32_t)c * csz;
-            const int Y = (int)(rem / W), j = (int)(rem - (uint32_t)Y * W);
-            const int cx = c & 3, cy = c >> 2;
-            const uint32_t w = st[i];
-            const uint32_t wr = cx < 3 ? st[i + csz]
-                                       : load16(st, (uint32_t)(4 * cy) * csz + (uint32_t)Y * W, W,
-                                                16 * j + 1 == Lq ? 0 : 16 * j + 1);
-            const uint32_t wd = cy == 0 ? st[i + 4 * csz] : st[(uint32_t)cx * csz + (uint32_t)(Y + 1 == H ? 0 : Y + 1) * W + j];
-            const uint32_t h = (w >> 1) & kM5, l = w & kM5;
-            const int sumS = __popc(h & ~l) - __popc(h & l);
-            const int sumG = __popc((h | l) ^ kM5) - __popc(l & ~h);
-            int bSS = 0, bss = 0;
-            bond_sums(h, l, (wr >> 1) & kM5, wr & kM5, bSS, bss);
-            bond_sums(h, l, (wd >> 1) & kM5, wd & kM5, bSS, bss);
-            const int sg = ((cx + cy) & 1) ? -1 : 1;
-            v[0] += sumS;
-            v[1] += __popc(h);
-            v[2] += bSS;
-            v[3] += bss;
-            v[4] += sumG;
-            v[5] += sg * sumG;
-            v[6] += sg * sumS;
-        }
+        obs_sums_2bit((const uint32_t *)d.state, L, v);
     }
     unsigned long long *o = out + 10 * (size_t)blockIdx.x;
     if (threadIdx.x < 10) o[threadIdx.x] = 0ull;
     __syncthreads();
     block_reduce_add<7>(v, o + 3);
     long long t3[3] = {0, 0, 0};
-    const long long *slots = (const long long *)(scr + kScrSlots);
-    for (int i = threadIdx.x; i < kMaxSlots; i += blockDim.x) {
-        t3[0] += slots[3 * i];
-        t3[1] += slots[3 * i + 1];
-        t3[2] += slots[3 * i + 2];
-    }
-    if (threadIdx.x == 0) {
-        const long long *base = (const long long *)(scr + kScrTrackBase);
-        t3[0] += base[0];
-        t3[1] += base[1];
-        t3[2] += base[2];
-    }
+    tracker_partial(scr, t3);
     block_reduce_add<3>(t3, o);
 }
 
@@ -586,12 +632,17 @@ hipError_t launch_sweep_lds(const BatchArgs &a, int max_L, int threads, bool wor
     if (threads > 0) block = (uint32_t)std::min(1024, std::max(64, threads / 64 * 64));
     if (block < 64u) block = 64u;
     const size_t lds = lds_state_words(max_L) * 4u;
-    if (word && block <= 512u)
+    // a.obs_out: the 512-thread word form writes the observables itself;
+    // the other forms are followed by the observables launch
+    if (word && block <= 512u) {
         hipLaunchKernelGGL(k_sweep_lds_w<512>, dim3((unsigned)a.count), dim3(block), lds, s, a);
-    else if (word)
+        return hipGetLastError();
+    }
+    if (word)
         hipLaunchKernelGGL(k_sweep_lds_w<1024>, dim3((unsigned)a.count), dim3(block), lds, s, a);
     else
         hipLaunchKernelGGL(k_sweep_lds, dim3((unsigned)a.count), dim3(block), lds, s, a);
+    if (a.obs_out) hipLaunchKernelGGL(k_obs_batch, dim3((unsigned)a.count), dim3(256), 0, s, a, a.obs_out);
     return hipGetLastError();
 }
 

@@ -86,10 +86,9 @@ int lattice_batch_graph_create(lattice *const *hs, int32_t count, uint32_t sweep
     int rc = LAT_OK;
     if (e == hipSuccess) {
         for (uint32_t k = 0; k < intervals && rc == LAT_OK; ++k) {
-            rc = enqueue_lds_sweeps(g->hs.data(), count, nullptr, sweeps, cs, /*tune=*/false);
-            if (rc == LAT_OK)
-                rc = enqueue_observables_batch(g->hs.data(), count,
-                                               (unsigned long long *)d_out + 10 * (size_t)count * k, cs);
+            // the sweeps and the interval's observables, in one launch for the word form
+            rc = enqueue_lds_sweeps(g->hs.data(), count, nullptr, sweeps, cs, /*tune=*/false,
+                                    (unsigned long long *)d_out + 10 * (size_t)count * k);
         }
         const hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
         if (rc == LAT_OK && e2 != hipSuccess) e = e2;

@@ -31,9 +31,12 @@ int hip_fail(hipError_t e, const char *what);
 bool live(const lattice *h);
 // Advance lattices resident in LDS; lattice i by sweeps[i] (null: `uniform`).
 // tune = false: no autotuning launches (the tuned or default block size),
-// as needed under stream capture.
+// as needed under stream capture.  obs_dev non-null: then also write the
+// lattices' observables into obs_dev (10 int64 each, as
+// enqueue_observables_batch), from LDS at the end of the 512-thread
+// word-form launch or by a separate launch after the other forms.
 int enqueue_lds_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps, uint32_t uniform,
-                       hipStream_t stream, bool tune = true);
+                       hipStream_t stream, bool tune = true, unsigned long long *obs_dev = nullptr);
 // One batched observables launch per 256 lattices into dev (10 int64 each).
 int enqueue_observables_batch(lattice *const *hs, int32_t count, unsigned long long *dev, hipStream_t stream);
 int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream);

@@ -85,6 +85,10 @@ struct BatchArgs {
     int count;
     uint8_t *scratch[kMaxBatch];
     uint32_t sweeps[kMaxBatch];
+    // non-null: after the sweeps, lattice b's observables and tracker total
+    // go to obs_out[10b ..] in k_obs_batch's layout (written by the sweep
+    // kernel itself in its 512-thread word form, else by k_obs_batch)
+    unsigned long long *obs_out;
 };
 
 // One phase of one sweep: phase p, displacement D = (r + 4m, 1 + 2k).

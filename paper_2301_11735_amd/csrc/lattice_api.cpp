@@ -470,7 +470,7 @@ int enqueue_observables_batch(lattice *const *hs, int32_t count, unsigned long l
 
 // Batched path: lattices resident in LDS, up to kMaxBatch per launch.
 int enqueue_lds_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps, uint32_t uniform,
-                       hipStream_t stream, bool tune)
+                       hipStream_t stream, bool tune, unsigned long long *obs_dev)
 {
     // LATTICE_LDS_SITE=1 keeps every batch on the per-site form (tests compare the two)
     const char *env = std::getenv("LATTICE_LDS_SITE");
@@ -492,8 +492,9 @@ int enqueue_lds_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps
         int slot = -1;
         const int threads = tune ? batch_threads_for(max_L, a.count, word, stream, &t0, &t1, &slot)
                                  : batch_threads_tuned(max_L, a.count, word);
+        a.obs_out = obs_dev ? obs_dev + 10 * (size_t)b : nullptr;
         if (t0) (void)hipEventRecord(t0, stream);
-        const hipError_t e = launch_sweep_lds(a, max_L, threads, word, stream);
+        hipError_t e = launch_sweep_lds(a, max_L, threads, word, stream);
         if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
         if (t1) {
             (void)hipEventRecord(t1, stream);
