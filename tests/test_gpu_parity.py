@@ -151,10 +151,11 @@ def test_mid_config_parity_first_sweeps():
     _run_parity(workloads.MID, [1, 2, 3])
 
 
-def test_large_config_parity_first_sweep():
+def test_large_config_parity_first_sweeps():
     """LARGE (L=8192, 2-bit) in the launch configuration the benchmark times:
-    the full state after one sweep, bit-exact."""
-    _run_parity(workloads.LARGE, [1])
+    the full state after one and after three sweeps (twelve phase launches,
+    each sweep with its own schedule), bit-exact."""
+    _run_parity(workloads.LARGE, [1, 3])
 
 
 def test_large_config_invariants():
