@@ -48,6 +48,19 @@ __device__ __forceinline__ uint32_t word_kq2(uint32_t A, uint32_t B)
     return (~(one | frozen) & kM5) | ((~frozen & kM5) << 1);
 }
 
+// Pair states of 8 pairs: nibble u of the result is code_a | code_b << 2 of
+// pair 8*half + u, for the aligned (a-word, b-word) couple (A, B).  One byte
+// permute gathers (A byte, B byte) pairs, then two swap stages interleave
+// their nibbles and 2-bit fields.
+__device__ __forceinline__ uint32_t pair_states8(uint32_t A, uint32_t B, int half)
+{
+    uint32_t x = __builtin_amdgcn_perm(B, A, half ? 0x07030602u : 0x05010400u);
+    uint32_t t = (x ^ (x >> 4)) & 0x00F000F0u;
+    x ^= t ^ (t << 4);
+    t = (x ^ (x >> 2)) & 0x0C0C0C0Cu;
+    return x ^ t ^ (t << 2);
+}
+
 __device__ __forceinline__ void stage_tables(uint2 *s_tab, uint2 *s_trans, const uint2 *__restrict__ g_tab,
                                              const uint2 *__restrict__ g_trans)
 {

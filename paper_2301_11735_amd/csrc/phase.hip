@@ -200,6 +200,7 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
         // and 3; handling them in that order keeps 8 packed words live.
         uint32_t dlo = 0u, dhi = 0u, packed = 0u;  // code changes of pairs 0-7 and 8-15
         const uint32_t kq2w = word_kq2(cw.A0, B0);
+        const uint32_t st8[2] = {pair_states8(cw.A0, B0, 0), pair_states8(cw.A0, B0, 1)};
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             uint32_t ge[4], go[4];
@@ -215,7 +216,7 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int t = 2 * c + h;
-                    const uint32_t s0 = ((cw.A0 >> (2 * t)) & 3u) | (((B0 >> (2 * t)) & 3u) << 2);
+                    const uint32_t s0 = (st8[t >> 3] >> (4 * (t & 7))) & 15u;
                     const uint32_t fields = 0x00030003u << (2 * (t & 7));
                     pair_step_delta(s0, (kq2w >> (2 * t)) & 3u, h ? go[k] : ge[k], h ? w.z : w.x, h ? w.w : w.y,
                                     s_transd, s_tab, fields, packed, t < 8 ? dlo : dhi);
