@@ -381,13 +381,17 @@ def test_word_and_site_batch_forms_agree(monkeypatch):
         assert oa.as_dict() == ob.as_dict()
 
 
-@pytest.mark.parametrize("kind", ["word", "site"])
-def test_batch_graph_replays_match_eager_and_oracle(kind):
+@pytest.mark.parametrize("kind,threads", [("word", 0), ("word", 512), ("word", 1024), ("site", 0)],
+                         ids=["word-auto", "word-512", "word-1024", "site"])
+def test_batch_graph_replays_match_eager_and_oracle(kind, threads, monkeypatch):
     """Observation intervals captured into a HIP graph: every replay (with
     eager batched work and synchronisation in between) leaves the lattices and
     every interval's observables exactly where the same eager calls do, and
-    where the oracle does."""
-    _say(f"case batch graph {kind}")
+    where the oracle does.  512-thread word blocks reduce the observables in
+    the sweep kernel, 1024-thread ones in a separate launch: both covered."""
+    if threads:
+        monkeypatch.setenv("LATTICE_BATCH_THREADS", str(threads))
+    _say(f"case batch graph {kind} threads={threads}")
     if kind == "word":
         specs = _word_batch_specs()
     else:
