@@ -309,3 +309,30 @@ def test_observables_of_known_configurations():
     assert o[0] == -1 and o[1] == 1 and o[2] == 0 and o[3] == 2 * N - 4 and o[4] == N - 1
     # site (5,3) has x+y even: the staggered spin sum (0 before) loses +1; the staggered charge is -1
     assert o[5] == -1 and o[6] == -1
+
+
+# ---------------------------------------------------------------- energy of eq. (3)
+@pytest.mark.parametrize("Delta,V,J", [(0.25, 0.75, 1.5), (-1.25, 0.5, -3.0), (2.0, -0.375, 0.5)])
+def test_energy_of_known_configurations(Delta, V, J):
+    """E = Delta sum S^2 + V sum_bonds S S + (J/4) sum_bonds sigma sigma
+    (eq. 3, 2N bonds) in closed form for configurations whose bond sums are
+    known by counting: the charge checkerboard (every bond +-), all sites +1,
+    the spin Neel state, all spins up, and the Neel state with one site made
+    a charge (its four bonds drop out of the spin sum).  Dyadic couplings keep
+    every value exact in FP64."""
+    L = 8
+    N = L * L
+    x, y = np.meshgrid(np.arange(L), np.arange(L))
+    par = ((x + y) % 2).reshape(-1)
+    cases = {
+        "checkerboard": (np.where(par == 0, 2, 3), Delta * N - 2 * V * N),
+        "all +1": (np.full(N, 2), Delta * N + 2 * V * N),
+        "neel": (par, -(J / 4) * 2 * N),
+        "all up": (np.zeros(N), (J / 4) * 2 * N),
+    }
+    defect = par.copy()
+    defect[2 * L + 3] = 2
+    cases["neel + one charge"] = (defect, Delta + (J / 4) * (-2 * N + 4))
+    for name, (codes, E) in cases.items():
+        codes = np.ascontiguousarray(codes, dtype=np.int8)
+        assert oracle.energy(Delta, V, J, oracle.observables(L, codes)) == E, name

@@ -88,6 +88,10 @@ def _pin_controller():
     mu_pins.test_controller_holds_the_charge_on_average()
 
 
+def _pin_energy():
+    model.test_energy_of_known_configurations(0.25, 0.75, 1.5)
+
+
 def _pin_map_chain():
     maps.test_map_mode_matches_exact_enumeration(4, 2, 1.0)
 
@@ -127,6 +131,12 @@ MUTANTS = [
     ("penalty controller pushes the wrong way", "*mu = *mu + kappa * (double)(Q - sumS) / (double)N;",
      "*mu = *mu + kappa * (double)(sumS - Q) / (double)N;", _pin_controller),
     ("penalty mode: neighbour spins ignored", "sG += SIG_OF[codes[nb[d]]];", ";", _pin_grand_canonical),
+    ("energy: J term without the 1/4 of eq. (3)",
+     "return Delta * (double)obs[1] + V * (double)obs[2] + 0.25 * J * (double)obs[3];",
+     "return Delta * (double)obs[1] + V * (double)obs[2] + J * (double)obs[3];", _pin_energy),
+    ("energy: charge-bond term with the wrong sign",
+     "return Delta * (double)obs[1] + V * (double)obs[2] + 0.25 * J * (double)obs[3];",
+     "return Delta * (double)obs[1] - V * (double)obs[2] + 0.25 * J * (double)obs[3];", _pin_energy),
     ("map step: a pair's configuration drawn with the acceptance word", "pairs[2 * i + 1], w[h], w[h + 1],",
      "pairs[2 * i + 1], w[h + 1], w[h + 1],", _pin_map_chain),
 ]
