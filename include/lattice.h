@@ -23,6 +23,9 @@
  *     memory; the library never allocates or frees device memory.
  *   - Return value 0 on success, or a negative LAT_E* code.  The text of the
  *     last error of the calling thread is returned by lattice_last_error().
+ *     No C++ exception crosses this interface: host memory exhaustion inside
+ *     a call is returned as LAT_ENOMEM, any other internal failure as
+ *     LAT_EHIP.
  *   - A handle is not thread-safe; all of its work is ordered on the stream
  *     given at creation.  Calls that return data to the host synchronise
  *     that stream.
@@ -39,7 +42,7 @@ extern "C" {
 
 #define LAT_OK 0
 #define LAT_EINVAL (-1) /* invalid argument (geometry, parameters, codes, null pointer) */
-#define LAT_ENOMEM (-2) /* a caller buffer is smaller than required */
+#define LAT_ENOMEM (-2) /* a caller buffer is smaller than required, or host memory ran out */
 #define LAT_EHIP (-3)   /* a HIP runtime call failed; see lattice_last_error() */
 #define LAT_ESTATE (-4) /* misuse: null or destroyed handle */
 
@@ -188,10 +191,12 @@ typedef struct lat_server lat_server;
 #define LAT_REQ_QUEUED 0
 #define LAT_REQ_RESIDENT 1
 #define LAT_REQ_FINISHED 2
+#define LAT_REQ_FAILED 3 /* could not be set up on the device; `error` says why */
 
 typedef struct {
     uint64_t id;
     int32_t status;          /* LAT_REQ_* */
+    int32_t error;           /* LAT_E* code of a failed request, else 0 */
     uint32_t sweeps_total;
     uint32_t sweeps_done;
     double t_submit, t_admit, t_finish;
@@ -212,17 +217,20 @@ typedef struct {
 int lat_server_create(void *d_pool, size_t pool_bytes, int32_t max_slots, uint64_t quantum_updates,
                       void *hip_stream, lat_server **out);
 /* Queue a request to run `sweeps` sweeps of the lattice p describes (p is
- * copied).  keep_state != 0 keeps the final codes for lat_server_poll.
- * Errors: LAT_ESTATE, LAT_EINVAL. */
+ * copied).  keep_state != 0 keeps the final codes for lat_server_poll.  The
+ * parameters get lattice_create's checks here, so a request that could never
+ * be set up is refused at once instead of reaching the queue.
+ * Errors: LAT_ESTATE, LAT_EINVAL (as lattice_create, or L > 512). */
 int lat_server_submit(lat_server *s, const lat_params *p, uint32_t sweeps, int32_t keep_state, uint64_t *id);
-/* Admit, advance every resident request once, harvest finished ones.
- * Synchronises the server's stream when requests are admitted or finish.
- * Errors: LAT_ESTATE, LAT_EHIP, and lattice_create's errors for a request. */
+/* Admit, advance every resident request once, harvest finished ones.  A
+ * request whose set-up fails at admission is marked LAT_REQ_FAILED (with its
+ * error code) and the queue moves on.  Synchronises the server's stream when
+ * requests are admitted or finish.  Errors: LAT_ESTATE, LAT_EHIP. */
 int lat_server_step(lat_server *s, int32_t *n_finished);
 /* State of a request; final_codes (N host codes, may be NULL) is filled for a
  * finished request submitted with keep_state.  Errors: LAT_ESTATE, LAT_EINVAL. */
 int lat_server_poll(lat_server *s, uint64_t id, lat_request_info *out, int8_t *final_codes);
-/* Forget a finished request.  Errors: LAT_ESTATE, LAT_EINVAL. */
+/* Forget a finished or failed request.  Errors: LAT_ESTATE, LAT_EINVAL. */
 int lat_server_release(lat_server *s, uint64_t id);
 int lat_server_stats(lat_server *s, lat_server_counters *out);
 /* Destroy the server and any resident lattices (caller memory untouched). */

@@ -45,7 +45,7 @@ EXPORTS = (
     "lat_server_stats",
     "lat_server_destroy",
 )
-REQ_QUEUED, REQ_RESIDENT, REQ_FINISHED = 0, 1, 2
+REQ_QUEUED, REQ_RESIDENT, REQ_FINISHED, REQ_FAILED = 0, 1, 2, 3
 MAP_ANY, MAP_NEIGHBOUR = 0, 1
 
 
@@ -93,6 +93,7 @@ class LatRequestInfo(ctypes.Structure):
     _fields_ = [
         ("id", ctypes.c_uint64),
         ("status", ctypes.c_int32),
+        ("error", ctypes.c_int32),
         ("sweeps_total", ctypes.c_uint32),
         ("sweeps_done", ctypes.c_uint32),
         ("t_submit", ctypes.c_double),

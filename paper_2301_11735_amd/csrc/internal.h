@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <string>
 
 #include "../../include/lattice.h"
@@ -28,7 +30,28 @@ namespace detail {
 
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
+// fail() for exception handlers: records "what: msg" without throwing (if
+// even that string cannot be allocated, a fixed message is kept instead).
+int fail_nothrow(int code, const char *what, const char *msg) noexcept;
 bool live(const lattice *h);
+
+// Runs the body of a C-ABI entry point so that no C++ exception crosses the
+// ABI: host memory exhaustion (std::bad_alloc) becomes LAT_ENOMEM, anything
+// else (a thread that cannot start, a container error) LAT_EHIP, each with a
+// message for lattice_last_error().
+template <class F>
+int guarded(const char *what, F &&body) noexcept
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return fail_nothrow(LAT_ENOMEM, what, "out of host memory");
+    } catch (const std::exception &e) {
+        return fail_nothrow(LAT_EHIP, what, e.what());
+    } catch (...) {
+        return fail_nothrow(LAT_EHIP, what, "unknown exception");
+    }
+}
 // Advance lattices resident in LDS; lattice i by sweeps[i] (null: `uniform`).
 // tune = false: no autotuning launches (the tuned or default block size),
 // as needed under stream capture.  obs_dev non-null: then also write the
@@ -40,6 +63,9 @@ int enqueue_lds_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps
 // One batched observables launch per 256 lattices into dev (10 int64 each).
 int enqueue_observables_batch(lattice *const *hs, int32_t count, unsigned long long *dev, hipStream_t stream);
 int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream);
+// Checks of lat_params (geometry, finite couplings, T > 0, the charge target
+// of eq. 2); writes the target charge and the charged count.
+int validate_params(const lat_params *p, int64_t *Q, int64_t *Nc);
 // v = (tracker nD, nV, nJ, sum S, sum S^2, bonds SS, bonds ss, M, M_st, C_st).
 void fill_obs(const lattice *h, const int64_t *v, lat_obs *out);
 

@@ -33,6 +33,7 @@ constexpr uint32_t kMagic = 0x1A771CEu;
 constexpr int kMaxL = 32768;
 
 thread_local std::string g_err;
+thread_local const char *g_err_fixed = nullptr;  // set when g_err could not be formatted
 
 }  // namespace
 
@@ -41,7 +42,19 @@ namespace detail {
 
 int fail(int code, const std::string &msg)
 {
+    g_err_fixed = nullptr;
     g_err = msg;
+    return code;
+}
+
+int fail_nothrow(int code, const char *what, const char *msg) noexcept
+{
+    try {
+        g_err_fixed = nullptr;
+        g_err = std::string(what) + ": " + msg;
+    } catch (...) {
+        g_err_fixed = code == LAT_ENOMEM ? "out of host memory" : "error (its message could not be stored)";
+    }
     return code;
 }
 
@@ -522,6 +535,35 @@ void fill_obs(const lattice *h, const int64_t *v, lat_obs *out)
     out->E = h->Delta * (double)out->n_charged + h->V * (double)out->bond_SS + 0.25 * h->J * (double)out->bond_ss;
 }
 
+// Parameter checks shared by lattice_create and the server's submit:
+// geometry, finite couplings, T > 0, and the charge target of eq. (2) (from
+// the given codes, which must lie in 0..3, or from n and n_charged).
+int validate_params(const lat_params *p, int64_t *Q_out, int64_t *Nc_out)
+{
+    if (!valid_geometry(p->L, p->encoding))
+        return fail(LAT_EINVAL, "invalid L for the encoding (int8: L%4==0; 2-bit: L%64==0; 4 <= L <= 32768)");
+    if (!std::isfinite(p->Delta) || !std::isfinite(p->V) || !std::isfinite(p->J) || !std::isfinite(p->T) ||
+        !std::isfinite(p->n))
+        return fail(LAT_EINVAL, "parameters must be finite");
+    if (!(p->T > 0.0)) return fail(LAT_EINVAL, "T must be > 0");
+    int64_t Q = 0, Nc = 0;
+    if (p->init_codes) {
+        const int64_t N = (int64_t)p->L * p->L;
+        for (int64_t i = 0; i < N; ++i) {
+            const int c = p->init_codes[i];
+            if (c < 0 || c > 3) return fail(LAT_EINVAL, "init code outside 0..3");
+            Q += c == 2 ? 1 : (c == 3 ? -1 : 0);
+            Nc += c >= 2;
+        }
+    } else {
+        const int rc = charge_target(p->L, p->n, p->n_charged, &Q, &Nc);
+        if (rc) return rc;
+    }
+    *Q_out = Q;
+    *Nc_out = Nc;
+    return LAT_OK;
+}
+
 }  // namespace detail
 }  // namespace lat
 
@@ -555,199 +597,211 @@ size_t lattice_scratch_bytes(int32_t L, int32_t encoding)
 
 int lattice_charge_target(int32_t L, double n, int64_t n_charged, int64_t *Q, int64_t *Nc)
 {
-    if (!Q || !Nc) return fail(LAT_EINVAL, "null output pointer");
-    if (L < 1 || L > kMaxL) return fail(LAT_EINVAL, "L out of range");
-    return charge_target(L, n, n_charged, Q, Nc);
+    return guarded("lattice_charge_target", [&]() -> int {
+        if (!Q || !Nc) return fail(LAT_EINVAL, "null output pointer");
+        if (L < 1 || L > kMaxL) return fail(LAT_EINVAL, "L out of range");
+        return charge_target(L, n, n_charged, Q, Nc);
+    });
 }
 
 int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void *d_scratch, size_t scratch_bytes,
                    void *hip_stream, lattice **out)
 {
-    g_err.clear();
-    if (!p || !out) return fail(LAT_EINVAL, "null params or output handle");
-    *out = nullptr;
-    if (!valid_geometry(p->L, p->encoding))
-        return fail(LAT_EINVAL, "invalid L for the encoding (int8: L%4==0; 2-bit: L%64==0; 4 <= L <= 32768)");
-    if (!std::isfinite(p->Delta) || !std::isfinite(p->V) || !std::isfinite(p->J) || !std::isfinite(p->T) ||
-        !std::isfinite(p->n))
-        return fail(LAT_EINVAL, "parameters must be finite");
-    if (!(p->T > 0.0)) return fail(LAT_EINVAL, "T must be > 0");
-    if (!d_state || !d_scratch) return fail(LAT_EINVAL, "null device buffer");
-    if (state_bytes < lattice_state_bytes(p->L, p->encoding)) return fail(LAT_ENOMEM, "state buffer too small");
-    if (scratch_bytes < kScrBytes) return fail(LAT_ENOMEM, "scratch buffer too small");
-
-    const int64_t N = (int64_t)p->L * p->L;
-    std::vector<int8_t> codes;
-    int64_t Q = 0, Nc = 0;
-    if (p->init_codes) {
-        codes.assign(p->init_codes, p->init_codes + N);
-        for (int64_t i = 0; i < N; ++i) {
-            const int c = codes[(size_t)i];
-            if (c < 0 || c > 3) return fail(LAT_EINVAL, "init code outside 0..3");
-            Q += c == 2 ? 1 : (c == 3 ? -1 : 0);
-            Nc += c >= 2;
-        }
-    } else {
-        const int rc = charge_target(p->L, p->n, p->n_charged, &Q, &Nc);
+    return guarded("lattice_create", [&]() -> int {
+        g_err.clear();
+        if (!p || !out) return fail(LAT_EINVAL, "null params or output handle");
+        *out = nullptr;
+        int64_t Q = 0, Nc = 0;
+        int rc = validate_params(p, &Q, &Nc);
         if (rc) return rc;
-        seeded_init(p->L, p->seed, (Nc + Q) / 2, (Nc - Q) / 2, codes);
-    }
-    std::vector<uint8_t> dev;
-    to_device_layout(p->L, p->encoding, codes, dev);
-    std::vector<uint32_t> tab, dev_tab, trans, trans_d;
-    build_threshold_table(p->Delta, p->V, p->J, p->T, tab);
-    build_device_table(tab, dev_tab);
-    build_transition_table(trans, trans_d);
-    {
-        static std::once_flag once;
-        static hipError_t init_err = hipSuccess;
-        std::call_once(once, [] {
-            init_err = init_kernel_attributes();
-            if (init_err == hipSuccess) init_err = init_map_kernel_attributes();
-        });
-        if (init_err != hipSuccess) return hip_fail(init_err, "kernel set-up");
-    }
+        if (!d_state || !d_scratch) return fail(LAT_EINVAL, "null device buffer");
+        if (state_bytes < lattice_state_bytes(p->L, p->encoding)) return fail(LAT_ENOMEM, "state buffer too small");
+        if (scratch_bytes < lattice_scratch_bytes(p->L, p->encoding)) return fail(LAT_ENOMEM, "scratch buffer too small");
 
-    lattice *h = new lattice();
-    h->L = p->L;
-    h->enc = p->encoding;
-    h->N = N;
-    h->Q = Q;
-    h->Nc = Nc;
-    h->n = p->n;
-    h->Delta = p->Delta;
-    h->V = p->V;
-    h->J = p->J;
-    h->T = p->T;
-    h->seed = p->seed;
-    h->start_sweep = p->start_sweep;
-    h->d_state = d_state;
-    h->d_scratch = (uint8_t *)d_scratch;
-    h->stream = (hipStream_t)hip_stream;
-    h->tuning = tuning_from_env();
-    {
-        const char *force = std::getenv("LATTICE_FORCE_PHASE_KERNELS");
-        h->phase_kernels = p->L > kLdsMaxL || (force && std::atoi(force) != 0);
-    }
-    h->magic = kMagic;
-    LatDesc desc{};
-    desc.state = d_state;
-    desc.L = p->L;
-    desc.enc = p->encoding;
-    desc.key0 = (uint32_t)p->seed;
-    desc.key1 = (uint32_t)(p->seed >> 32);
-    desc.next_sweep = p->start_sweep;
+        const int64_t N = (int64_t)p->L * p->L;
+        std::vector<int8_t> codes;
+        if (p->init_codes)
+            codes.assign(p->init_codes, p->init_codes + N);
+        else
+            seeded_init(p->L, p->seed, (Nc + Q) / 2, (Nc - Q) / 2, codes);
+        std::vector<uint8_t> dev;
+        to_device_layout(p->L, p->encoding, codes, dev);
+        std::vector<uint32_t> tab, dev_tab, trans, trans_d;
+        build_threshold_table(p->Delta, p->V, p->J, p->T, tab);
+        build_device_table(tab, dev_tab);
+        build_transition_table(trans, trans_d);
+        {
+            static std::once_flag once;
+            static hipError_t init_err = hipSuccess;
+            std::call_once(once, [] {
+                init_err = init_kernel_attributes();
+                if (init_err == hipSuccess) init_err = init_map_kernel_attributes();
+            });
+            if (init_err != hipSuccess) return hip_fail(init_err, "kernel set-up");
+        }
 
-    hipError_t e = hipMemcpyAsync(d_state, dev.data(), dev.size(), hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(h->d_scratch + kScrDevTab, dev_tab.data(), dev_tab.size() * 4, hipMemcpyHostToDevice,
-                           h->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(h->d_scratch + kScrTrans, trans.data(), trans.size() * 4, hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(h->d_scratch + kScrTransD, trans_d.data(), trans_d.size() * 4, hipMemcpyHostToDevice,
-                           h->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(h->d_scratch + kScrFullTab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(h->d_scratch + kScrDesc, &desc, sizeof(desc), hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess) e = launch_zero_i64((unsigned long long *)(h->d_scratch + kScrTrack), 11, h->stream);
-    if (e == hipSuccess) e = launch_zero_i64((unsigned long long *)(h->d_scratch + kScrTrackBase), 3, h->stream);
-    if (e == hipSuccess) e = launch_zero_i64((unsigned long long *)(h->d_scratch + kScrSlots), 3 * kMaxSlots, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // host staging buffers die with this frame
-    if (e != hipSuccess) {
-        h->magic = 0;
-        delete h;
-        return hip_fail(e, "lattice_create");
-    }
-    *out = h;
-    return LAT_OK;
+        lattice *h = new lattice();
+        h->L = p->L;
+        h->enc = p->encoding;
+        h->N = N;
+        h->Q = Q;
+        h->Nc = Nc;
+        h->n = p->n;
+        h->Delta = p->Delta;
+        h->V = p->V;
+        h->J = p->J;
+        h->T = p->T;
+        h->seed = p->seed;
+        h->start_sweep = p->start_sweep;
+        h->d_state = d_state;
+        h->d_scratch = (uint8_t *)d_scratch;
+        h->stream = (hipStream_t)hip_stream;
+        h->tuning = tuning_from_env();
+        {
+            const char *force = std::getenv("LATTICE_FORCE_PHASE_KERNELS");
+            h->phase_kernels = p->L > kLdsMaxL || (force && std::atoi(force) != 0);
+        }
+        h->magic = kMagic;
+        LatDesc desc{};
+        desc.state = d_state;
+        desc.L = p->L;
+        desc.enc = p->encoding;
+        desc.key0 = (uint32_t)p->seed;
+        desc.key1 = (uint32_t)(p->seed >> 32);
+        desc.next_sweep = p->start_sweep;
+
+        hipError_t e = hipMemcpyAsync(d_state, dev.data(), dev.size(), hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->d_scratch + kScrDevTab, dev_tab.data(), dev_tab.size() * 4, hipMemcpyHostToDevice,
+                               h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->d_scratch + kScrTrans, trans.data(), trans.size() * 4, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->d_scratch + kScrTransD, trans_d.data(), trans_d.size() * 4, hipMemcpyHostToDevice,
+                               h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->d_scratch + kScrFullTab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->d_scratch + kScrDesc, &desc, sizeof(desc), hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = launch_zero_i64((unsigned long long *)(h->d_scratch + kScrTrack), 11, h->stream);
+        if (e == hipSuccess) e = launch_zero_i64((unsigned long long *)(h->d_scratch + kScrTrackBase), 3, h->stream);
+        if (e == hipSuccess) e = launch_zero_i64((unsigned long long *)(h->d_scratch + kScrSlots), 3 * kMaxSlots, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // host staging buffers die with this frame
+        if (e != hipSuccess) {
+            h->magic = 0;
+            delete h;
+            return hip_fail(e, "lattice_create");
+        }
+        *out = h;
+        return LAT_OK;
+    });
 }
 
 int lattice_sweep(lattice *h, uint32_t sweeps)
 {
-    if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
-    return enqueue_sweeps(h, sweeps, h->stream);
+    return guarded("lattice_sweep", [&]() -> int {
+        if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
+        return enqueue_sweeps(h, sweeps, h->stream);
+    });
 }
 
 int lattice_sweep_batch(lattice *const *hs, int32_t count, uint32_t sweeps, void *hip_stream)
 {
-    if (count < 0 || (count > 0 && !hs)) return fail(LAT_EINVAL, "bad batch");
-    for (int32_t i = 0; i < count; ++i)
-        if (!live(hs[i])) return fail(LAT_ESTATE, "null or destroyed handle in batch");
-    {
-        std::vector<const lattice *> seen(hs, hs + count);
-        std::sort(seen.begin(), seen.end());
-        if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
-            return fail(LAT_EINVAL, "a lattice appears twice in the batch");
-    }
-    if (sweeps == 0) return LAT_OK;
-    std::vector<lattice *> small;
-    for (int32_t i = 0; i < count; ++i) {
-        if (hs[i]->phase_kernels) {
-            const int rc = enqueue_phase_sweeps(hs[i], sweeps, (hipStream_t)hip_stream);
-            if (rc) return rc;
-        } else {
-            small.push_back(hs[i]);
+    return guarded("lattice_sweep_batch", [&]() -> int {
+        if (count < 0 || (count > 0 && !hs)) return fail(LAT_EINVAL, "bad batch");
+        for (int32_t i = 0; i < count; ++i)
+            if (!live(hs[i])) return fail(LAT_ESTATE, "null or destroyed handle in batch");
+        {
+            std::vector<const lattice *> seen(hs, hs + count);
+            std::sort(seen.begin(), seen.end());
+            if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+                return fail(LAT_EINVAL, "a lattice appears twice in the batch");
         }
-    }
-    return enqueue_lds_sweeps(small.data(), (int32_t)small.size(), nullptr, sweeps, (hipStream_t)hip_stream);
+        if (sweeps == 0) return LAT_OK;
+        std::vector<lattice *> small;
+        for (int32_t i = 0; i < count; ++i) {
+            if (hs[i]->phase_kernels) {
+                const int rc = enqueue_phase_sweeps(hs[i], sweeps, (hipStream_t)hip_stream);
+                if (rc) return rc;
+            } else {
+                small.push_back(hs[i]);
+            }
+        }
+        return enqueue_lds_sweeps(small.data(), (int32_t)small.size(), nullptr, sweeps, (hipStream_t)hip_stream);
+    });
 }
 
 int lattice_observables_batch(lattice *const *hs, int32_t count, void *d_out, size_t out_bytes, lat_obs *out,
                               void *hip_stream)
 {
-    if (count < 0 || (count > 0 && (!hs || !out || !d_out))) return fail(LAT_EINVAL, "bad batch");
-    if (out_bytes < (size_t)count * 80u) return fail(LAT_ENOMEM, "output buffer smaller than 80 bytes per lattice");
-    for (int32_t i = 0; i < count; ++i)
-        if (!live(hs[i])) return fail(LAT_ESTATE, "null or destroyed handle in batch");
-    hipStream_t stream = (hipStream_t)hip_stream;
-    const int rc = enqueue_observables_batch(hs, count, (unsigned long long *)d_out, stream);
-    if (rc) return rc;
-    std::vector<int64_t> v((size_t)count * 10);
-    hipError_t e = hipSuccess;
-    if (count > 0) e = hipMemcpyAsync(v.data(), d_out, v.size() * 8, hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hip_fail(e, "lattice_observables_batch");
-    for (int32_t i = 0; i < count; ++i) fill_obs(hs[i], &v[10 * (size_t)i], &out[i]);
-    return LAT_OK;
+    return guarded("lattice_observables_batch", [&]() -> int {
+        if (count < 0 || (count > 0 && (!hs || !out || !d_out))) return fail(LAT_EINVAL, "bad batch");
+        if (out_bytes < (size_t)count * 80u) return fail(LAT_ENOMEM, "output buffer smaller than 80 bytes per lattice");
+        for (int32_t i = 0; i < count; ++i)
+            if (!live(hs[i])) return fail(LAT_ESTATE, "null or destroyed handle in batch");
+        hipStream_t stream = (hipStream_t)hip_stream;
+        const int rc = enqueue_observables_batch(hs, count, (unsigned long long *)d_out, stream);
+        if (rc) return rc;
+        std::vector<int64_t> v((size_t)count * 10);
+        hipError_t e = hipSuccess;
+        if (count > 0) e = hipMemcpyAsync(v.data(), d_out, v.size() * 8, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        // lattices swept by the persistent kernel: its bounded device-wide
+        // barrier flags a time-out in the lattice's error word
+        for (int32_t i = 0; i < count && e == hipSuccess; ++i) {
+            if (!hs[i]->phase_kernels || !hs[i]->tuning.persistent) continue;
+            uint32_t err = 0;
+            e = hipMemcpy(&err, hs[i]->d_scratch + kScrErr, sizeof(err), hipMemcpyDeviceToHost);
+            if (e == hipSuccess && (err & 1u))
+                return fail(LAT_EHIP, "a device-wide phase barrier timed out; the state is invalid");
+        }
+        if (e != hipSuccess) return hip_fail(e, "lattice_observables_batch");
+        for (int32_t i = 0; i < count; ++i) fill_obs(hs[i], &v[10 * (size_t)i], &out[i]);
+        return LAT_OK;
+    });
 }
 
 int lattice_observables(lattice *h, lat_obs *out)
 {
-    if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
-    if (!out) return fail(LAT_EINVAL, "null output");
-    unsigned long long *track = (unsigned long long *)(h->d_scratch + kScrTrack);
-    hipError_t e = launch_observables(h->d_scratch, h->d_state, h->L, h->enc, h->stream);
-    int64_t v[11];  // tracker, 7 sums, error flags
-    if (e == hipSuccess) e = hipMemcpyAsync(v, track, sizeof(v), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return hip_fail(e, "lattice_observables");
-    if ((uint32_t)v[10] & 1u) return fail(LAT_EHIP, "a device-wide phase barrier timed out; the state is invalid");
-    fill_obs(h, v, out);
-    return LAT_OK;
+    return guarded("lattice_observables", [&]() -> int {
+        if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
+        if (!out) return fail(LAT_EINVAL, "null output");
+        unsigned long long *track = (unsigned long long *)(h->d_scratch + kScrTrack);
+        hipError_t e = launch_observables(h->d_scratch, h->d_state, h->L, h->enc, h->stream);
+        int64_t v[11];  // tracker, 7 sums, error flags
+        if (e == hipSuccess) e = hipMemcpyAsync(v, track, sizeof(v), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(e, "lattice_observables");
+        if ((uint32_t)v[10] & 1u) return fail(LAT_EHIP, "a device-wide phase barrier timed out; the state is invalid");
+        fill_obs(h, v, out);
+        return LAT_OK;
+    });
 }
 
 int lattice_read_state(lattice *h, int8_t *host_codes)
 {
-    if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
-    if (!host_codes) return fail(LAT_EINVAL, "null output");
-    std::vector<uint8_t> dev(lattice_state_bytes(h->L, h->enc));
-    hipError_t e = hipMemcpyAsync(dev.data(), h->d_state, dev.size(), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return hip_fail(e, "lattice_read_state");
-    from_device_layout(h->L, h->enc, dev, host_codes);
-    return LAT_OK;
+    return guarded("lattice_read_state", [&]() -> int {
+        if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
+        if (!host_codes) return fail(LAT_EINVAL, "null output");
+        std::vector<uint8_t> dev(lattice_state_bytes(h->L, h->enc));
+        hipError_t e = hipMemcpyAsync(dev.data(), h->d_state, dev.size(), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(e, "lattice_read_state");
+        from_device_layout(h->L, h->enc, dev, host_codes);
+        return LAT_OK;
+    });
 }
 
 int lattice_destroy(lattice *h)
 {
-    if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
-    h->magic = 0;
-    delete h;
-    return LAT_OK;
+    return guarded("lattice_destroy", [&]() -> int {
+        if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
+        h->magic = 0;
+        delete h;
+        return LAT_OK;
+    });
 }
 
-const char *lattice_last_error(void) { return g_err.c_str(); }
+const char *lattice_last_error(void) { return g_err_fixed ? g_err_fixed : g_err.c_str(); }
 
 }  // extern "C"

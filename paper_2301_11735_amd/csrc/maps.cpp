@@ -56,23 +56,27 @@ extern "C" {
 
 int lattice_map_steps(lattice *h, uint64_t first_map, uint32_t n_maps, int32_t partner)
 {
-    if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
-    if (partner != LAT_MAP_ANY && partner != LAT_MAP_NEIGHBOUR) return fail(LAT_EINVAL, "unknown partner rule");
-    lattice *one[1] = {h};
-    const int rc = check_batch(one, 1);
-    if (rc) return rc;
-    if (n_maps == 0) return LAT_OK;
-    return enqueue_map_steps(one, 1, first_map, n_maps, partner, h->stream);
+    return guarded("lattice_map_steps", [&]() -> int {
+        if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
+        if (partner != LAT_MAP_ANY && partner != LAT_MAP_NEIGHBOUR) return fail(LAT_EINVAL, "unknown partner rule");
+        lattice *one[1] = {h};
+        const int rc = check_batch(one, 1);
+        if (rc) return rc;
+        if (n_maps == 0) return LAT_OK;
+        return enqueue_map_steps(one, 1, first_map, n_maps, partner, h->stream);
+    });
 }
 
 int lattice_map_steps_batch(lattice *const *hs, int32_t count, uint64_t first_map, uint32_t n_maps, int32_t partner,
                             void *hip_stream)
 {
-    if (partner != LAT_MAP_ANY && partner != LAT_MAP_NEIGHBOUR) return fail(LAT_EINVAL, "unknown partner rule");
-    const int rc = check_batch(hs, count);
-    if (rc) return rc;
-    if (n_maps == 0 || count == 0) return LAT_OK;
-    return enqueue_map_steps(hs, count, first_map, n_maps, partner, (hipStream_t)hip_stream);
+    return guarded("lattice_map_steps_batch", [&]() -> int {
+        if (partner != LAT_MAP_ANY && partner != LAT_MAP_NEIGHBOUR) return fail(LAT_EINVAL, "unknown partner rule");
+        const int rc = check_batch(hs, count);
+        if (rc) return rc;
+        if (n_maps == 0 || count == 0) return LAT_OK;
+        return enqueue_map_steps(hs, count, first_map, n_maps, partner, (hipStream_t)hip_stream);
+    });
 }
 
 }  // extern "C"

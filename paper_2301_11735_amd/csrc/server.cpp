@@ -96,6 +96,7 @@ struct Request {
     std::vector<int8_t> init;  // copy of p->init_codes, if any
     uint32_t sweeps = 0, done = 0;
     int32_t status = LAT_REQ_QUEUED;
+    int32_t error = 0;  // LAT_E* code of a failed request
     size_t off = 0, bytes = 0;
     lattice *h = nullptr;
     lat_obs obs{};
@@ -142,8 +143,16 @@ int admit(lat_server *s)
         p.init_codes = r.init.empty() ? nullptr : r.init.data();
         const int rc = lattice_create(&p, s->pool + off, sb, s->pool + off + align_up(sb), cb, s->stream, &r.h);
         if (rc) {
+            // the request cannot run (e.g. a HIP error at its set-up): it is
+            // reported as failed and the queue moves on, so one bad request
+            // never holds up the others
             s->alloc->release(off, r.bytes);
-            return rc;
+            r.h = nullptr;
+            r.status = LAT_REQ_FAILED;
+            r.error = rc;
+            r.t_finish = now_s();
+            s->queue.pop_front();
+            continue;
         }
         r.status = LAT_REQ_RESIDENT;
         r.t_admit = now_s();
@@ -160,157 +169,178 @@ extern "C" {
 int lat_server_create(void *d_pool, size_t pool_bytes, int32_t max_slots, uint64_t quantum_updates,
                       void *hip_stream, lat_server **out)
 {
-    if (!out || !d_pool || max_slots <= 0 || quantum_updates == 0) return fail(LAT_EINVAL, "bad server arguments");
-    *out = nullptr;
-    const size_t obs_bytes = align_up((size_t)max_slots * 80u);
-    if (pool_bytes <= obs_bytes) return fail(LAT_ENOMEM, "pool smaller than the observables slot");
-    auto *s = new lat_server();
-    s->pool = (uint8_t *)d_pool;
-    s->pool_bytes = pool_bytes;
-    s->obs_off = 0;
-    s->max_slots = max_slots;
-    s->quantum = quantum_updates;
-    s->stream = (hipStream_t)hip_stream;
-    s->alloc = std::make_unique<PoolAllocator>(pool_bytes);
-    size_t off;
-    s->alloc->alloc(obs_bytes, &off);  // offset 0: reserved for observables
-    *out = s;
-    return LAT_OK;
+    return guarded("lat_server_create", [&]() -> int {
+        if (!out || !d_pool || max_slots <= 0 || quantum_updates == 0) return fail(LAT_EINVAL, "bad server arguments");
+        *out = nullptr;
+        const size_t obs_bytes = align_up((size_t)max_slots * 80u);
+        if (pool_bytes <= obs_bytes) return fail(LAT_ENOMEM, "pool smaller than the observables slot");
+        auto *s = new lat_server();
+        s->pool = (uint8_t *)d_pool;
+        s->pool_bytes = pool_bytes;
+        s->obs_off = 0;
+        s->max_slots = max_slots;
+        s->quantum = quantum_updates;
+        s->stream = (hipStream_t)hip_stream;
+        s->alloc = std::make_unique<PoolAllocator>(pool_bytes);
+        size_t off;
+        s->alloc->alloc(obs_bytes, &off);  // offset 0: reserved for observables
+        *out = s;
+        return LAT_OK;
+    });
 }
 
 int lat_server_submit(lat_server *s, const lat_params *p, uint32_t sweeps, int32_t keep_state, uint64_t *id)
 {
-    if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
-    if (!p || !id || sweeps == 0) return fail(LAT_EINVAL, "bad request");
-    if (p->L > kLdsMaxL || lattice_state_bytes(p->L, p->encoding) == 0)
-        return fail(LAT_EINVAL, "served lattices need a valid L <= 512");
-    if (!(p->T > 0.0)) return fail(LAT_EINVAL, "T must be > 0");
-    auto r = std::make_unique<Request>();
-    r->id = s->next_id++;
-    r->params = *p;
-    if (p->init_codes) r->init.assign(p->init_codes, p->init_codes + (size_t)p->L * p->L);
-    r->params.init_codes = nullptr;
-    r->sweeps = sweeps;
-    r->keep_state = keep_state != 0;
-    r->t_submit = now_s();
-    *id = r->id;
-    s->queue.push_back(r->id);
-    s->reqs[r->id] = std::move(r);
-    return LAT_OK;
+    return guarded("lat_server_submit", [&]() -> int {
+        if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
+        if (!p || !id || sweeps == 0) return fail(LAT_EINVAL, "bad request");
+        if (p->L > kLdsMaxL || lattice_state_bytes(p->L, p->encoding) == 0)
+            return fail(LAT_EINVAL, "served lattices need a valid L <= 512");
+        // the checks lattice_create makes, so that a request that could never
+        // be admitted is refused here rather than at admission
+        int64_t Q = 0, Nc = 0;
+        const int rc = validate_params(p, &Q, &Nc);
+        if (rc) return rc;
+        auto r = std::make_unique<Request>();
+        r->id = s->next_id++;
+        r->params = *p;
+        if (p->init_codes) r->init.assign(p->init_codes, p->init_codes + (size_t)p->L * p->L);
+        r->params.init_codes = nullptr;
+        r->sweeps = sweeps;
+        r->keep_state = keep_state != 0;
+        r->t_submit = now_s();
+        *id = r->id;
+        s->queue.push_back(r->id);
+        s->reqs[r->id] = std::move(r);
+        return LAT_OK;
+    });
 }
 
 int lat_server_step(lat_server *s, int32_t *n_finished)
 {
-    if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
-    int rc = admit(s);
-    if (rc) return rc;
-    if (n_finished) *n_finished = 0;
-    if (s->resident.empty()) return LAT_OK;
-
-    std::vector<lattice *> hs;
-    std::vector<uint32_t> sw;
-    for (uint64_t id : s->resident) {
-        Request &r = *s->reqs[id];
-        const uint64_t N = (uint64_t)r.params.L * r.params.L;
-        const uint32_t want = (uint32_t)std::max<uint64_t>(1, s->quantum / (N + kSweepCostSites));
-        const uint32_t k = std::min(want, r.sweeps - r.done);
-        hs.push_back(r.h);
-        sw.push_back(k);
-        r.done += k;
-        s->site_updates += N * k;
-    }
-    rc = enqueue_lds_sweeps(hs.data(), (int32_t)hs.size(), sw.data(), 0, s->stream);
-    if (rc) return rc;
-    ++s->steps;
-
-    std::vector<lattice *> fin;
-    std::vector<uint64_t> fin_ids, keep;
-    for (uint64_t id : s->resident) {
-        Request &r = *s->reqs[id];
-        if (r.done >= r.sweeps) {
-            fin.push_back(r.h);
-            fin_ids.push_back(id);
-        } else {
-            keep.push_back(id);
-        }
-    }
-    if (!fin.empty()) {
-        std::vector<lat_obs> obs(fin.size());
-        rc = lattice_observables_batch(fin.data(), (int32_t)fin.size(), s->pool + s->obs_off,
-                                       (size_t)s->max_slots * 80u, obs.data(), s->stream);
+    return guarded("lat_server_step", [&]() -> int {
+        if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
+        int rc = admit(s);
         if (rc) return rc;
-        const double t = now_s();
-        for (size_t i = 0; i < fin.size(); ++i) {
-            Request &r = *s->reqs[fin_ids[i]];
-            r.obs = obs[i];
-            if (r.keep_state) {
-                r.final_codes.resize((size_t)r.params.L * r.params.L);
-                rc = lattice_read_state(r.h, r.final_codes.data());
-                if (rc) return rc;
-            }
-            lattice_destroy(r.h);
-            r.h = nullptr;
-            s->alloc->release(r.off, r.bytes);
-            r.status = LAT_REQ_FINISHED;
-            r.t_finish = t;
+        if (n_finished) *n_finished = 0;
+        if (s->resident.empty()) return LAT_OK;
+
+        std::vector<lattice *> hs;
+        std::vector<uint32_t> sw;
+        for (uint64_t id : s->resident) {
+            Request &r = *s->reqs[id];
+            const uint64_t N = (uint64_t)r.params.L * r.params.L;
+            const uint32_t want = (uint32_t)std::max<uint64_t>(1, s->quantum / (N + kSweepCostSites));
+            const uint32_t k = std::min(want, r.sweeps - r.done);
+            hs.push_back(r.h);
+            sw.push_back(k);
+            r.done += k;
+            s->site_updates += N * k;
         }
-    }
-    s->resident = keep;
-    if (n_finished) *n_finished = (int32_t)fin.size();
-    return LAT_OK;
+        rc = enqueue_lds_sweeps(hs.data(), (int32_t)hs.size(), sw.data(), 0, s->stream);
+        if (rc) return rc;
+        ++s->steps;
+
+        std::vector<lattice *> fin;
+        std::vector<uint64_t> fin_ids, keep;
+        for (uint64_t id : s->resident) {
+            Request &r = *s->reqs[id];
+            if (r.done >= r.sweeps) {
+                fin.push_back(r.h);
+                fin_ids.push_back(id);
+            } else {
+                keep.push_back(id);
+            }
+        }
+        if (!fin.empty()) {
+            std::vector<lat_obs> obs(fin.size());
+            rc = lattice_observables_batch(fin.data(), (int32_t)fin.size(), s->pool + s->obs_off,
+                                           (size_t)s->max_slots * 80u, obs.data(), s->stream);
+            if (rc) return rc;
+            const double t = now_s();
+            for (size_t i = 0; i < fin.size(); ++i) {
+                Request &r = *s->reqs[fin_ids[i]];
+                r.obs = obs[i];
+                if (r.keep_state) {
+                    r.final_codes.resize((size_t)r.params.L * r.params.L);
+                    rc = lattice_read_state(r.h, r.final_codes.data());
+                    if (rc) return rc;
+                }
+                lattice_destroy(r.h);
+                r.h = nullptr;
+                s->alloc->release(r.off, r.bytes);
+                r.status = LAT_REQ_FINISHED;
+                r.t_finish = t;
+            }
+        }
+        s->resident = keep;
+        if (n_finished) *n_finished = (int32_t)fin.size();
+        return LAT_OK;
+    });
 }
 
 int lat_server_poll(lat_server *s, uint64_t id, lat_request_info *out, int8_t *final_codes)
 {
-    if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
-    auto it = s->reqs.find(id);
-    if (it == s->reqs.end() || !out) return fail(LAT_EINVAL, "unknown request");
-    const Request &r = *it->second;
-    out->id = r.id;
-    out->status = r.status;
-    out->sweeps_total = r.sweeps;
-    out->sweeps_done = r.done;
-    out->t_submit = r.t_submit;
-    out->t_admit = r.t_admit;
-    out->t_finish = r.t_finish;
-    out->obs = r.obs;
-    if (final_codes && r.status == LAT_REQ_FINISHED) {
-        if (!r.keep_state) return fail(LAT_EINVAL, "request was submitted without keep_state");
-        std::memcpy(final_codes, r.final_codes.data(), r.final_codes.size());
-    }
-    return LAT_OK;
+    return guarded("lat_server_poll", [&]() -> int {
+        if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
+        auto it = s->reqs.find(id);
+        if (it == s->reqs.end() || !out) return fail(LAT_EINVAL, "unknown request");
+        const Request &r = *it->second;
+        out->id = r.id;
+        out->status = r.status;
+        out->error = r.error;
+        out->sweeps_total = r.sweeps;
+        out->sweeps_done = r.done;
+        out->t_submit = r.t_submit;
+        out->t_admit = r.t_admit;
+        out->t_finish = r.t_finish;
+        out->obs = r.obs;
+        if (final_codes && r.status == LAT_REQ_FINISHED) {
+            if (!r.keep_state) return fail(LAT_EINVAL, "request was submitted without keep_state");
+            std::memcpy(final_codes, r.final_codes.data(), r.final_codes.size());
+        }
+        return LAT_OK;
+    });
 }
 
 int lat_server_release(lat_server *s, uint64_t id)
 {
-    if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
-    auto it = s->reqs.find(id);
-    if (it == s->reqs.end() || it->second->status != LAT_REQ_FINISHED) return fail(LAT_EINVAL, "not finished");
-    s->reqs.erase(it);
-    return LAT_OK;
+    return guarded("lat_server_release", [&]() -> int {
+        if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
+        auto it = s->reqs.find(id);
+        if (it == s->reqs.end() ||
+            (it->second->status != LAT_REQ_FINISHED && it->second->status != LAT_REQ_FAILED))
+            return fail(LAT_EINVAL, "not finished");
+        s->reqs.erase(it);
+        return LAT_OK;
+    });
 }
 
 int lat_server_stats(lat_server *s, lat_server_counters *out)
 {
-    if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
-    if (!out) return fail(LAT_EINVAL, "null output");
-    out->queued = (int32_t)s->queue.size();
-    out->resident = (int32_t)s->resident.size();
-    out->pool_used = s->alloc->used();
-    out->steps = s->steps;
-    out->site_updates = s->site_updates;
-    return LAT_OK;
+    return guarded("lat_server_stats", [&]() -> int {
+        if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
+        if (!out) return fail(LAT_EINVAL, "null output");
+        out->queued = (int32_t)s->queue.size();
+        out->resident = (int32_t)s->resident.size();
+        out->pool_used = s->alloc->used();
+        out->steps = s->steps;
+        out->site_updates = s->site_updates;
+        return LAT_OK;
+    });
 }
 
 int lat_server_destroy(lat_server *s)
 {
-    if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
-    hipError_t e = hipStreamSynchronize(s->stream);
-    for (auto &kv : s->reqs)
-        if (kv.second->h) lattice_destroy(kv.second->h);
-    s->alloc.reset();
-    delete s;
-    return e == hipSuccess ? LAT_OK : hip_fail(e, "lat_server_destroy");
+    return guarded("lat_server_destroy", [&]() -> int {
+        if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
+        hipError_t e = hipStreamSynchronize(s->stream);
+        for (auto &kv : s->reqs)
+            if (kv.second->h) lattice_destroy(kv.second->h);
+        s->alloc.reset();
+        delete s;
+        return e == hipSuccess ? LAT_OK : hip_fail(e, "lat_server_destroy");
+    });
 }
 
 }  // extern "C"

@@ -40,7 +40,7 @@ def serve(requests, pool_bytes, slots, quantum, keep_state=False, progress=True)
 
     srv = lat.Server(pool_bytes, max_slots=slots, quantum_updates=quantum)
     t0 = time.monotonic()
-    i, pending, done = 0, {}, {}
+    i, pending, done, failed = 0, {}, {}, {}
     last_report = t0
     while i < len(requests) or pending:
         now = time.monotonic() - t0
@@ -52,7 +52,11 @@ def serve(requests, pool_bytes, slots, quantum, keep_state=False, progress=True)
             pending[rid] = r
             i += 1
         if pending:
-            if srv.step() > 0:
+            finished = srv.step()
+            st = srv.stats() if finished == 0 else None
+            # poll when requests finished, or when some left the server without
+            # finishing (a request whose set-up failed at admission)
+            if finished > 0 or st.queued + st.resident < len(pending):
                 for rid in list(pending):
                     res = srv.poll(rid, with_state=keep_state)
                     info, codes = res if keep_state else (res, None)
@@ -61,6 +65,10 @@ def serve(requests, pool_bytes, slots, quantum, keep_state=False, progress=True)
                         done[r.index] = dict(arrival=r.arrival_s, admit=info.t_admit - t0, finish=info.t_finish - t0,
                                              latency=info.t_finish - t0 - r.arrival_s, obs=info.obs.as_dict(),
                                              codes=codes, L=r.spec.L, sweeps=r.spec.sweeps)
+                        srv.release(rid)
+                    elif info.status == lat.REQ_FAILED:
+                        r = pending.pop(rid)
+                        failed[r.index] = info.error
                         srv.release(rid)
         elif i < len(requests):
             time.sleep(max(0.0, min(0.01, requests[i].arrival_s - (time.monotonic() - t0))))
@@ -73,6 +81,9 @@ def serve(requests, pool_bytes, slots, quantum, keep_state=False, progress=True)
     wall = time.monotonic() - t0
     st = srv.stats()
     srv.destroy()
+    if failed:
+        print(f"[serve] {len(failed)} requests failed at admission: {sorted(failed.items())[:8]}", file=sys.stderr,
+              flush=True)
     return done, wall, st
 
 

@@ -128,3 +128,76 @@ def test_penalty_calls_on_null_handles_fail_cleanly():
     L = lat.lib()
     mu = ctypes.c_double(0.0)
     assert L.lattice_mu_sweeps(None, 0, 1, 0.5, ctypes.byref(mu), None, None) == lat.LAT_ESTATE
+
+
+def _server_without_device():
+    """A server whose pool pointer is never dereferenced: submit only queues."""
+    h = ctypes.c_void_p()
+    rc = lat.lib().lat_server_create(ctypes.c_void_p(1 << 20), 1 << 20, 4, 1 << 16, None, ctypes.byref(h))
+    assert rc == lat.LAT_OK
+    return h
+
+
+@pytest.mark.parametrize("kw", [dict(n=1.5), dict(Delta=float("nan")), dict(V=float("inf")), dict(T=0.0),
+                                dict(n=0.5, n_charged=4), dict(n_charged=64 * 64 + 2), dict(L=96),
+                                dict(L=1024)])
+def test_server_refuses_a_request_that_could_never_be_admitted(kw):
+    """Bad parameters are refused at submit (LAT_EINVAL), so that they never
+    reach admission, where they would block the queue; good requests before
+    and after them still queue."""
+    srv = _server_without_device()
+    good = lat.LatParams(L=64, encoding=1, n=0.1, Delta=0.25, V=0.5, J=1.0, T=0.8, seed=1, n_charged=-1,
+                         start_sweep=0, init_codes=None)
+    rid = ctypes.c_uint64()
+    assert lat.lib().lat_server_submit(srv, ctypes.byref(good), 10, 0, ctypes.byref(rid)) == lat.LAT_OK
+    bad = lat.LatParams(L=64, encoding=1, n=0.1, Delta=0.25, V=0.5, J=1.0, T=0.8, seed=2, n_charged=-1,
+                        start_sweep=0, init_codes=None)
+    for k, v in kw.items():
+        setattr(bad, k, v)
+    assert lat.lib().lat_server_submit(srv, ctypes.byref(bad), 10, 0, ctypes.byref(rid)) == lat.LAT_EINVAL
+    assert lat.lib().lattice_last_error().decode()
+    assert lat.lib().lat_server_submit(srv, ctypes.byref(good), 10, 0, ctypes.byref(rid)) == lat.LAT_OK
+    st = lat.LatServerStats()
+    assert lat.lib().lat_server_stats(srv, ctypes.byref(st)) == lat.LAT_OK
+    assert st.queued == 2
+
+
+def test_server_refuses_init_codes_outside_the_code_range():
+    srv = _server_without_device()
+    codes = (ctypes.c_int8 * (64 * 64))(*([0] * (64 * 64 - 1) + [5]))
+    p = lat.LatParams(L=64, encoding=1, n=0.0, Delta=0.25, V=0.5, J=1.0, T=0.8, seed=1, n_charged=-1,
+                      start_sweep=0, init_codes=ctypes.cast(codes, ctypes.POINTER(ctypes.c_int8)))
+    rid = ctypes.c_uint64()
+    assert lat.lib().lat_server_submit(srv, ctypes.byref(p), 10, 0, ctypes.byref(rid)) == lat.LAT_EINVAL
+
+
+_ENOMEM_CHILD = r"""
+import ctypes, resource, sys
+sys.path.insert(0, {root!r})
+import paper_2301_11735_amd as lat
+L = lat.lib()
+limit = 3 << 30
+resource.setrlimit(resource.RLIMIT_AS, (limit, limit))
+p = lat.LatParams(L=16384, encoding=1, n=0.1, Delta=0.25, V=0.5, J=1.0, T=0.8, seed=1, n_charged=-1,
+                  start_sweep=0, init_codes=None)
+h = ctypes.c_void_p()
+rc = L.lattice_create(ctypes.byref(p), ctypes.c_void_p(1 << 20), 1 << 40, ctypes.c_void_p(1 << 20), 1 << 40, None,
+                      ctypes.byref(h))
+print(rc, L.lattice_last_error().decode(), h.value, flush=True)
+"""
+
+
+def test_host_memory_exhaustion_is_an_error_code_not_an_abort():
+    """The seeded init of an L=16384 lattice needs about 4.6 GB of host
+    memory; under a 3 GiB address-space limit the allocation fails before any
+    device call, and the C-ABI returns LAT_ENOMEM instead of letting the C++
+    exception terminate the caller."""
+    import subprocess
+    import sys
+
+    out = subprocess.run([sys.executable, "-c", _ENOMEM_CHILD.format(root=ROOT)], capture_output=True, text=True,
+                         timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    rc, rest = out.stdout.split(" ", 1)
+    assert int(rc) == lat.LAT_ENOMEM, out.stdout
+    assert "out of host memory" in rest and rest.strip().endswith("None")
