@@ -28,7 +28,7 @@ GCC_FLAGS = ["-O2", "-fPIC", "-shared", "-std=c11", "-ffp-contract=off", "-fno-f
 def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so next to it (gcc, host only)."""
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        tmp = _LIB_PATH + ".tmp"
+        tmp = f"{_LIB_PATH}.tmp{os.getpid():x}"  # per process: parallel test workers may build at once
         subprocess.check_call(["gcc", *GCC_FLAGS, "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH

@@ -443,10 +443,12 @@ int64_t orc_map_pairs(int32_t L)
     return n < 1 ? 1 : n;
 }
 
-/* Build map m.  The paper's steps: start with every site unmarked; draw a
- * site at random until an unmarked one comes up, mark it (site a); the same
- * for site b; add the pair (a, b); mark the nearest neighbours of a and of b;
- * repeat until the map holds orc_map_pairs(L) pairs.
+/* Build map m (section 3.2): pairs are accepted one at a time until the map
+ * holds orc_map_pairs(L) of them.  Each site of a pair is the first draw that
+ * lands on a site not yet marked; the first site is marked before its
+ * partner is drawn, so a pair's two sites differ but may be neighbours; once
+ * both are chosen, their neighbours are marked too, so no later pair can
+ * touch or border an earlier one.
  * Draw k of map m is site mulhi(w, N) with w = word (k mod 4) of the Philox
  * counter (m_lo, DOM_MAP, floor(k/4), m_hi).  Writes pairs[2i] = a_i and
  * pairs[2i+1] = b_i; returns the number of draws consumed, or -1 if L < 3. */

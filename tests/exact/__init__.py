@@ -20,7 +20,7 @@ _LIB = os.path.join(_HERE, "libexact.so")
 
 def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+        tmp = f"{_LIB}.tmp{os.getpid():x}"
         subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
@@ -77,7 +77,7 @@ def build_philox_pin(force: bool = True) -> str | None:
     if not os.path.exists(os.path.join(ROCM_INCLUDE, "rocrand", "rocrand_philox4x32_10.h")):
         return None
     if force or not os.path.exists(_PIN_LIB) or os.path.getmtime(_PIN_LIB) < os.path.getmtime(_PIN_SRC):
-        tmp = _PIN_LIB + ".tmp"
+        tmp = f"{_PIN_LIB}.tmp{os.getpid():x}"
         subprocess.check_call(["g++", "-O1", "-fPIC", "-shared", "-D__HIP_PLATFORM_AMD__",
                                "-I" + ROCM_INCLUDE, "-o", tmp, _PIN_SRC])
         os.replace(tmp, _PIN_LIB)
