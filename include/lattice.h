@@ -90,8 +90,10 @@ typedef struct {
  * Returns 0 if L is not valid for the encoding. */
 size_t lattice_state_bytes(int32_t L, int32_t encoding);
 
-/* Bytes of the device scratch buffer a lattice needs (threshold table,
- * energy tracker, reduction slots).  Independent of L. */
+/* Bytes of the device scratch buffer a lattice needs: threshold and
+ * transition tables, energy tracker, reduction slots (88 KiB), plus, for an
+ * int8 lattice with L % 64 == 0, N/4 bytes for the 2-bit copy its sweeps
+ * run on when it is swept by the multi-block kernels. */
 size_t lattice_scratch_bytes(int32_t L, int32_t encoding);
 
 /* Charge target of eq. (2) for side L and density n (Q rounded to the
@@ -122,6 +124,22 @@ int lattice_sweep(lattice *h, uint32_t sweeps);
  * incremental energy tracker, and fill *out (E in FP64 on the host).
  * Synchronises the handle's stream.  Errors: LAT_ESTATE, LAT_EINVAL, LAT_EHIP. */
 int lattice_observables(lattice *h, lat_obs *out);
+
+/* An observation series kept on the device: `intervals` times, advance the
+ * lattice by `every` sweeps and reduce its observables (as
+ * lattice_observables) into record k of d_series, with no host
+ * synchronisation in between.  Record k is 88 bytes at byte 88k: 11 int64,
+ * the tracker (nD, nV, nJ), the 7 sums in lat_obs order from sum_S to
+ * C_stag, and the sweep index after the interval (start_sweep + sweeps
+ * done).  d_series is caller-owned device memory of at least 88*intervals
+ * bytes.  Asynchronous on the handle's stream; read the records with
+ * lattice_series_read.  Errors: LAT_ESTATE, LAT_EINVAL (every == 0, null
+ * d_series), LAT_ENOMEM (d_series too small), LAT_EHIP. */
+int lattice_sweep_series(lattice *h, uint32_t intervals, uint32_t every, void *d_series, size_t series_bytes);
+/* Synchronise the handle's stream and convert `intervals` records of
+ * d_series (written by lattice_sweep_series on this handle) into out.
+ * Errors: LAT_ESTATE, LAT_EINVAL, LAT_EHIP. */
+int lattice_series_read(lattice *h, const void *d_series, uint32_t intervals, lat_obs *out);
 
 /* Copy the configuration to N host codes in the canonical row-major layout.
  * Synchronises the handle's stream.  Errors: LAT_ESTATE, LAT_EINVAL, LAT_EHIP. */

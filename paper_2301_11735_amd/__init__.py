@@ -26,6 +26,8 @@ EXPORTS = (
     "lattice_sweep",
     "lattice_observables",
     "lattice_read_state",
+    "lattice_sweep_series",
+    "lattice_series_read",
     "lattice_sweep_batch",
     "lattice_observables_batch",
     "lattice_batch_graph_create",
@@ -145,6 +147,10 @@ def lib() -> ctypes.CDLL:
         L.lattice_observables.restype = ctypes.c_int
         L.lattice_read_state.argtypes = [vp, ctypes.POINTER(ctypes.c_int8)]
         L.lattice_read_state.restype = ctypes.c_int
+        L.lattice_sweep_series.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, vp, sz]
+        L.lattice_sweep_series.restype = ctypes.c_int
+        L.lattice_series_read.argtypes = [vp, vp, ctypes.c_uint32, ctypes.POINTER(LatObs)]
+        L.lattice_series_read.restype = ctypes.c_int
         L.lattice_sweep_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_uint32, vp]
         L.lattice_sweep_batch.restype = ctypes.c_int
         L.lattice_observables_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, vp, sz, ctypes.POINTER(LatObs), vp]
@@ -276,6 +282,22 @@ class Lattice:
     def map_steps(self, first_map: int, n_maps: int = 1, partner: int = 0):
         """Apply maps first_map .. first_map+n_maps-1 of the map mode (partner MAP_ANY or MAP_NEIGHBOUR)."""
         _check(lib().lattice_map_steps(self.handle, first_map, n_maps, partner))
+
+    def sweep_series(self, intervals: int, every: int = 1, read: bool = True):
+        """`intervals` times: `every` sweeps, then the observables into a device
+        record (no host synchronisation between intervals).  Returns the
+        records as a list of LatObs (read=True), else the device buffer for
+        read_series()."""
+        import torch
+
+        buf = torch.empty(88 * max(1, intervals), dtype=torch.uint8, device=self.state.device)
+        _check(lib().lattice_sweep_series(self.handle, intervals, every, buf.data_ptr(), buf.numel()))
+        return self.read_series(buf, intervals) if read else buf
+
+    def read_series(self, buf, intervals: int) -> list:
+        out = (LatObs * max(1, intervals))()
+        _check(lib().lattice_series_read(self.handle, buf.data_ptr(), intervals, out))
+        return list(out)[:intervals]
 
     def observables(self) -> LatObs:
         o = LatObs()

@@ -7,6 +7,7 @@
 #include <algorithm>
 
 #include "device_common.h"
+#include "word_task.h"
 
 namespace lat {
 namespace {
@@ -147,234 +148,6 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(BatchArgs args)
     unstage_lattice(lat, d, g);
     if (threadIdx.x == 0) ((LatDesc *)(scr + kScrDesc))->next_sweep = d.next_sweep + my_sweeps;
     block_reduce_add<3>(tr, (unsigned long long *)(scr + kScrTrackBase));
-}
-
-// ---------------------------------------------------------------------------
-// Batched sweeps, word-parallel form, for lattices with L % 64 == 0: the LDS
-// copy has the global 2-bit class layout (W = L/64 words per class row), and
-// a phase is computed 16 sites at a time as in the single-lattice phase
-// kernel.  The 16 pairs of an a-word are split among Q threads (Q = 1, 2, 4
-// or 8, chosen per lattice so that the block is filled): thread q of a word
-// takes the Philox calls c with c % Q == q, i.e. sites 2c and 2c+1.
-//
-// Within a phase no updated site neighbours another updated site, so every
-// neighbour word read is constant during the phase; the a-word and the two
-// b-words a thread updates are shared with other threads only in bit fields
-// that those threads neither read nor write, and the updates are applied as
-// LDS xor atomics of the changed bits (a plain store when Q = 1 for the a-word).
-
-struct WordPhase {
-    uint32_t oA0, oAL, oAR, oAV, oB0, oBL, oBR, oBV;  // class offsets (words)
-    int W, H, Lq, dX, k, p, pb;
-    uint32_t magicW;                                 // ceil(2^32 / W)
-    uint32_t s_lo, s_hi, key0, key1;
-};
-
-// Barrier = true keeps the compiler from interleaving the Philox calls of a
-// task (fewer live registers, needed at 1024 threads per block); without it
-// the calls overlap each other's LDS table lookups.
-// Value of the lane XOR lanes away (XOR = 1, 2: quad permutes; 4: any lane).
-template <int XOR>
-__device__ __forceinline__ uint32_t lane_xor(uint32_t v)
-{
-    if constexpr (XOR == 1)
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
-    else if constexpr (XOR == 2)
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
-    else
-        return (uint32_t)__shfl_xor((int)v, XOR, 64);
-}
-
-// Philox calls a task makes: all 8 of its word (Q = 1) or 8/Q of them.  The
-// i-th is call_of_task(q, i), in the order word_task uses them.
-template <int Q>
-constexpr int kTaskCalls = Q == 1 ? 8 : 8 / Q;
-template <int Q>
-__device__ __forceinline__ int call_of_task(int q, int i)
-{
-    if constexpr (Q == 1) return i < 4 ? 2 * i : 2 * (i - 4) + 1;
-    else if constexpr (Q == 2) return 2 * i + q;
-    else return 2 * ((q >> 1) + 2 * i) + (q & 1);
-}
-
-// First counter word of a task's word (its a-word's first Philox call): the
-// same in every phase, since each phase's a-class has the same shape.
-template <int Q>
-__device__ __forceinline__ uint32_t task_call0(const WordPhase &f, uint32_t task)
-{
-    constexpr int LOGQ = Q == 1 ? 0 : Q == 2 ? 1 : Q == 4 ? 2 : 3;
-    const uint32_t wi = task >> LOGQ;
-    const int Y = f.W == 1 ? (int)wi : (int)__umulhi(wi, f.magicW), j = (int)wi - Y * f.W;
-    return (uint32_t)Y * (uint32_t)(f.Lq >> 1) + 8u * (uint32_t)j;
-}
-
-// Pipe: the task's draws for this phase are given in pre[], and those of the
-// next phase (sweep ns, phase np) are computed here, between the phase's
-// dependent LDS lookups, and returned in pre[].
-template <int Q, bool Barrier, bool Pipe = false>
-__device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uint32_t task, const uint2 *s_tab,
-                                          const uint4 *s_transd, int (&tr)[3], u32x4 *pre = nullptr,
-                                          uint64_t ns = 0, int np = 0)
-{
-    constexpr int LOGQ = Q == 1 ? 0 : Q == 2 ? 1 : Q == 4 ? 2 : 3;
-    const uint32_t wi = task >> LOGQ;
-    const int q = (int)(task & (uint32_t)(Q - 1));
-    const int W = f.W, H = f.H, Lq = f.Lq;
-    const int Y = W == 1 ? (int)wi : (int)__umulhi(wi, f.magicW), j = (int)wi - Y * W;
-    int Xb = 16 * j + f.dX;
-    if (Xb >= Lq) Xb -= Lq;
-    const int Yb = Y + f.k >= H ? Y + f.k - H : Y + f.k;
-    const int xAL = f.p > 0 ? 16 * j : (j == 0 ? Lq - 1 : 16 * j - 1);
-    const int xAR = f.p < 3 ? 16 * j : 16 * j + 1;
-    const int xBL = f.pb > 0 ? Xb : (Xb == 0 ? Lq - 1 : Xb - 1);
-    const int xBR = f.pb < 3 ? Xb : (Xb + 1 == Lq ? 0 : Xb + 1);
-    const uint32_t ro = (uint32_t)Y * W, rob = (uint32_t)Yb * W;
-    const uint32_t roU = (uint32_t)(Y == 0 ? H - 1 : Y - 1) * W;
-    const uint32_t robD = (uint32_t)(Yb + 1 == H ? 0 : Yb + 1) * W;
-
-    const uint32_t A0 = lat[f.oA0 + ro + j];
-    const uint32_t B0 = load16(lat, f.oB0 + rob, W, Xb);
-    SideSums sa, sb;
-    if constexpr (Q == 1) {
-        sa = side_sums(load16(lat, f.oAL + ro, W, xAL), load16(lat, f.oAR + ro, W, xAR), lat[f.oAV + roU + j],
-                       lat[f.oAV + ro + j]);
-        sb = side_sums(load16(lat, f.oBL + rob, W, xBL), load16(lat, f.oBR + rob, W, xBR),
-                       load16(lat, f.oBV + rob, W, Xb), load16(lat, f.oBV + robD, W, Xb));
-    } else {
-        // The Q threads of a word are Q consecutive lanes.  Lanes of the
-        // first half sum a-side neighbour words, the others b-side ones,
-        // 8/Q words each; the partial sums (additive, nibble-wide) are
-        // combined within the group and the two sides exchanged.
-        const int side = q >= Q / 2;
-        const int k0 = (q % (Q / 2)) * (8 / Q);
-        const uint32_t base[4] = {side ? f.oBL + rob : f.oAL + ro, side ? f.oBR + rob : f.oAR + ro,
-                                  side ? f.oBV + rob : f.oAV + roU, side ? f.oBV + robD : f.oAV + ro};
-        const int xs[4] = {side ? xBL : xAL, side ? xBR : xAR, side ? Xb : 16 * j, side ? Xb : 16 * j};
-        SideSums part{0u, 0u, 0u, 0u};
-#pragma unroll
-        for (int i = 0; i < 8 / Q; ++i) {
-            const int kk = k0 + i;
-            const uint32_t b = kk == 0 ? base[0] : kk == 1 ? base[1] : kk == 2 ? base[2] : base[3];
-            const int x = kk == 0 ? xs[0] : kk == 1 ? xs[1] : kk == 2 ? xs[2] : xs[3];
-            side_add(part, load16(lat, b, W, x));
-        }
-        SideSums full = part, other;
-        if constexpr (Q >= 4) {
-            full.ES += lane_xor<1>(part.ES);
-            full.OS += lane_xor<1>(part.OS);
-            full.EG += lane_xor<1>(part.EG);
-            full.OG += lane_xor<1>(part.OG);
-        }
-        if constexpr (Q == 8) {
-            full.ES += lane_xor<2>(full.ES);
-            full.OS += lane_xor<2>(full.OS);
-            full.EG += lane_xor<2>(full.EG);
-            full.OG += lane_xor<2>(full.OG);
-        }
-        other.ES = lane_xor<Q / 2>(full.ES);
-        other.OS = lane_xor<Q / 2>(full.OS);
-        other.EG = lane_xor<Q / 2>(full.EG);
-        other.OG = lane_xor<Q / 2>(full.OG);
-        sa = side ? other : full;
-        sb = side ? full : other;
-    }
-
-    const uint32_t call0 = (uint32_t)Y * (uint32_t)(Lq >> 1) + 8u * (uint32_t)j;
-    // code changes of pairs 0-7 (dlo) and 8-15 (dhi): site a's in the low
-    // half, site b's in the high half
-    uint32_t dlo = 0u, dhi = 0u, packed = 0u;
-    const uint32_t kq2w = word_kq2(A0, B0);
-    u32x4 nxt[kTaskCalls<Q>];
-    if constexpr (Pipe) {
-#pragma unroll
-        for (int i = 0; i < kTaskCalls<Q>; ++i)
-            nxt[i] = philox4x32_10((uint32_t)ns, (uint32_t)np, call0 + (uint32_t)call_of_task<Q>(q, i),
-                                   (uint32_t)(ns >> 32), f.key0, f.key1);
-    }
-    auto do_call = [&](int i, int c, uint32_t be, uint32_t bo, uint32_t &dacc) {
-        const u32x4 w =
-            Pipe ? pre[i] : philox4x32_10(f.s_lo, (uint32_t)f.p, call0 + (uint32_t)c, f.s_hi, f.key0, f.key1);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int t = 2 * c + h;
-            const uint32_t s0 = ((A0 >> (2 * t)) & 3u) | (((B0 >> (2 * t)) & 3u) << 2);
-            pair_step_delta(s0, (kq2w >> (2 * t)) & 3u, h ? bo : be, h ? w.z : w.x, h ? w.w : w.y, s_transd, s_tab,
-                            0x00030003u << (2 * (t & 7)), packed, dacc);
-        }
-    };
-    if constexpr (Q <= 2) {
-#pragma unroll
-        for (int hh = 0; hh < (Q == 1 ? 2 : 1); ++hh) {
-            const int half = Q == 1 ? hh : q;
-            const int sh = 4 * half;
-            uint32_t ge[4], go[4];
-            transpose4((sa.ES >> sh) & kM0F, (sb.ES >> sh) & kM0F, (sa.EG >> sh) & kM0F, (sb.EG >> sh) & kM0F,
-                       ge[0], ge[1], ge[2], ge[3]);
-            transpose4((sa.OS >> sh) & kM0F, (sb.OS >> sh) & kM0F, (sa.OG >> sh) & kM0F, (sb.OG >> sh) & kM0F,
-                       go[0], go[1], go[2], go[3]);
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {  // pairs 4kk .. 4kk+3
-                const int slot = Q == 1 ? 4 * hh + kk : kk;
-                if (kk < 2)
-                    do_call(slot, 2 * kk + half, ge[kk], go[kk], dlo);
-                else
-                    do_call(slot, 2 * kk + half, ge[kk], go[kk], dhi);
-                if (Barrier) __builtin_amdgcn_sched_barrier(0);
-            }
-        }
-    } else {
-        const int half = q & 1, sh = 4 * half;
-        const uint32_t rES0 = (sa.ES >> sh) & kM0F, rES1 = (sb.ES >> sh) & kM0F;
-        const uint32_t rEG0 = (sa.EG >> sh) & kM0F, rEG1 = (sb.EG >> sh) & kM0F;
-        const uint32_t rOS0 = (sa.OS >> sh) & kM0F, rOS1 = (sb.OS >> sh) & kM0F;
-        const uint32_t rOG0 = (sa.OG >> sh) & kM0F, rOG1 = (sb.OG >> sh) & kM0F;
-        uint32_t dx = 0u;  // Q = 8: pairs 4kk .. 4kk+3 of the one call, kk = q >> 1
-#pragma unroll
-        for (int i = 0; i < 8 / Q; ++i) {  // Q = 4: i = 0 covers pairs 0-7, i = 1 pairs 8-15
-            const uint32_t kk = (uint32_t)(q >> 1) + 2u * (uint32_t)i;
-            const uint32_t sel = kk | ((4u + kk) << 8) | 0x0C0C0000u;
-            do_call(i, 2 * (int)kk + half, gather_byte(rES0, rES1, rEG0, rEG1, sel),
-                    gather_byte(rOS0, rOS1, rOG0, rOG1, sel), Q == 8 ? dx : (i == 0 ? dlo : dhi));
-        }
-        if (Q == 8) {
-            dlo = (q >> 1) < 2 ? dx : 0u;
-            dhi = (q >> 1) < 2 ? 0u : dx;
-        }
-    }
-    const uint32_t dA = __builtin_amdgcn_perm(dhi, dlo, 0x05040100u);
-    const uint32_t dB = __builtin_amdgcn_perm(dhi, dlo, 0x07060302u);
-    if constexpr (Pipe) {
-#pragma unroll
-        for (int i = 0; i < kTaskCalls<Q>; ++i) pre[i] = nxt[i];
-    }
-    unpack_tracker(packed, tr);
-    const int jb = Xb >> 4, shb = Xb & 15;
-    if constexpr (!Barrier) {
-        // unconditional (an XOR with 0 changes nothing): branches on the
-        // masks cost more than the LDS operations they would skip
-        if (Q == 1)
-            lat[f.oA0 + ro + j] = A0 ^ dA;
-        else
-            atomicXor(&lat[f.oA0 + ro + j], dA);
-        atomicXor(&lat[f.oB0 + rob + (uint32_t)jb], dB << (2 * shb));
-        const uint32_t hi = shb ? dB >> (32 - 2 * shb) : 0u;
-        atomicXor(&lat[f.oB0 + rob + (uint32_t)(jb + 1 == W ? 0 : jb + 1)], hi);
-    } else {
-        // the 1024-thread build keeps the branches: without them it needs
-        // more registers than 16 waves a compute unit leave
-        if (Q == 1) {
-            if (dA) lat[f.oA0 + ro + j] = A0 ^ dA;
-        } else if (dA) {
-            atomicXor(&lat[f.oA0 + ro + j], dA);
-        }
-        if (dB) {
-            atomicXor(&lat[f.oB0 + rob + (uint32_t)jb], dB << (2 * shb));
-            if (shb) {
-                const uint32_t hi = dB >> (32 - 2 * shb);
-                if (hi) atomicXor(&lat[f.oB0 + rob + (uint32_t)(jb + 1 == W ? 0 : jb + 1)], hi);
-            }
-        }
-    }
 }
 
 template <int Q, bool Barrier>

@@ -57,7 +57,9 @@ int lattice_batch_graph_create(lattice *const *hs, int32_t count, uint32_t sweep
             return fail(LAT_ENOMEM, "output buffer smaller than 80 bytes per lattice and interval");
         for (int32_t i = 0; i < count; ++i) {
             if (!live(hs[i])) return fail(LAT_ESTATE, "null or destroyed handle in batch");
-            if (hs[i]->phase_kernels) return fail(LAT_EINVAL, "a batch graph takes lattices with L <= 512 only");
+            if (hs[i]->path == kPathPhase)
+                return fail(LAT_EINVAL, "a batch graph takes lattices on the on-chip or the multi-block word path "
+                                        "(L <= 2048 with L % 64 == 0, or L <= 512)");
         }
         {
             std::vector<const lattice *> seen(hs, hs + count);
@@ -86,10 +88,20 @@ int lattice_batch_graph_create(lattice *const *hs, int32_t count, uint32_t sweep
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
         int rc = LAT_OK;
         if (e == hipSuccess) {
+            std::vector<lattice *> small, big;
+            for (lattice *h : g->hs) (h->path == kPathLds ? small : big).push_back(h);
             for (uint32_t k = 0; k < intervals && rc == LAT_OK; ++k) {
-                // the sweeps and the interval's observables, in one launch for the word form
-                rc = enqueue_lds_sweeps(g->hs.data(), count, nullptr, sweeps, cs, /*tune=*/false,
-                                        (unsigned long long *)d_out + 10 * (size_t)count * k);
+                unsigned long long *slot = (unsigned long long *)d_out + 10 * (size_t)count * k;
+                if (big.empty()) {
+                    // the sweeps and the interval's observables, in one launch for the word form
+                    rc = enqueue_lds_sweeps(g->hs.data(), count, nullptr, sweeps, cs, /*tune=*/false, slot);
+                } else {
+                    // the multi-block word path computes its schedules on the
+                    // device, so its launch series replays like the on-chip one
+                    rc = enqueue_lds_sweeps(small.data(), (int32_t)small.size(), nullptr, sweeps, cs, false);
+                    if (rc == LAT_OK) rc = enqueue_offchip_sweeps(big.data(), (int32_t)big.size(), nullptr, sweeps, cs);
+                    if (rc == LAT_OK) rc = enqueue_observables_batch(g->hs.data(), count, slot, cs);
+                }
             }
             const hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
             if (rc == LAT_OK && e2 != hipSuccess) e = e2;

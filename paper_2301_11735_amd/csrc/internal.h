@@ -12,6 +12,16 @@
 #include "../../include/lattice.h"
 #include "kernels.h"
 
+// How a lattice is swept (chosen at create from L and the encoding):
+//   kPathLds    one block holds the whole lattice in LDS for all the sweeps of
+//               a launch (batch.hip); L <= 512;
+//   kPathWords  one launch per phase, many blocks per lattice, Q lanes per
+//               a-word, schedule computed on the device (words.hip); L % 64 == 0;
+//   kPathPhase  one launch per phase, one thread per a-word (phase.hip).
+// Int8 lattices with L % 64 == 0 on the last two paths are swept on a 2-bit
+// copy in their scratch (packed before the sweeps of a call, unpacked after).
+enum : int { kPathLds = 0, kPathWords = 1, kPathPhase = 2 };
+
 struct lattice {
     int L = 0, enc = 0;
     int64_t N = 0, Q = 0, Nc = 0;
@@ -21,7 +31,8 @@ struct lattice {
     uint8_t *d_scratch = nullptr;
     hipStream_t stream = nullptr;
     lat::Tuning2Bit tuning{0, 0, 0, 0};
-    bool phase_kernels = false;  // big lattice, or forced: one launch per phase
+    int path = kPathLds;
+    bool packed = false;  // int8 swept on the 2-bit copy at scratch + kScrWork
     uint32_t magic = 0;
 };
 
@@ -62,7 +73,11 @@ int enqueue_lds_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps
                        hipStream_t stream, bool tune = true, unsigned long long *obs_dev = nullptr);
 // One batched observables launch per 256 lattices into dev (10 int64 each).
 int enqueue_observables_batch(lattice *const *hs, int32_t count, unsigned long long *dev, hipStream_t stream);
-int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream);
+// Lattices on the off-chip paths (words, phase): lattice i by sweeps[i]
+// (null: `uniform`); int8 ones are packed before and unpacked after.
+// convert = false: packed lattices are already on (and stay on) their copy.
+int enqueue_offchip_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps, uint32_t uniform,
+                           hipStream_t stream, bool convert = true);
 // Checks of lat_params (geometry, finite couplings, T > 0, the charge target
 // of eq. 2); writes the target charge and the charged count.
 int validate_params(const lat_params *p, int64_t *Q, int64_t *Nc);

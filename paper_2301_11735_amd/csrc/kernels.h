@@ -65,6 +65,13 @@ constexpr size_t kScrMuTab = kScrFullTab + ((size_t)kTabSize * 4 + 255) / 256 * 
 constexpr size_t kScrTransD = kScrMuTab + ((size_t)kMuTabSize * 4 + 255) / 256 * 256;  // 88576
 constexpr size_t kScrBytes = kScrTransD + (size_t)kTransEntries * 16;                 // 90112
 
+// Int8 lattices with L % 64 == 0 that are swept by the phase kernels keep a
+// copy of their state in the 2-bit class layout (N/4 bytes) after the fixed
+// part of their scratch: the sweeps of a call run on that copy, which is
+// packed from the int8 codes before them and unpacked into them after.
+constexpr size_t kScrWork = kScrBytes;
+inline bool int8_packs(int L, int enc) { return enc == 0 && L % 64 == 0; }
+
 // Per-lattice descriptor kept in the lattice's scratch, read by the batched
 // kernel.  next_sweep is advanced on the device by every path that sweeps.
 struct LatDesc {
@@ -104,6 +111,37 @@ struct PhaseArgs {
     uint32_t s_lo, s_hi;
 };
 
+// One phase of up to kWordsBatch lattices in the 2-bit class layout (int8
+// ones through their packed copy), spread over many blocks per lattice:
+// blocks first_block[i] .. first_block[i+1]-1 update lattice i, Q lanes per
+// a-word.  Sweep iter of the series (sweep next_sweep + iter of each lattice,
+// schedule computed on the device); a lattice with sweeps[i] <= iter is
+// skipped.  Block b of a lattice adds its tracker sums to tracker slot b.
+constexpr int kWordsBatch = 64;
+constexpr int kWordsThreads = 256;
+struct WordsArgs {
+    int count;
+    int p;
+    uint32_t iter;
+    uint8_t *scratch[kWordsBatch];
+    uint32_t sweeps[kWordsBatch];
+    uint32_t first_block[kWordsBatch + 1];
+};
+// Lanes per a-word for side L (fewer for larger lattices, whose words fill
+// the chip anyway), and the blocks one lattice takes.
+int words_lanes(int L);
+inline uint32_t words_blocks(int L, int Q)
+{
+    const uint32_t tasks = (uint32_t)Q * (uint32_t)L * (uint32_t)L / 128u;
+    return (tasks + kWordsThreads - 1) / kWordsThreads;
+}
+hipError_t launch_phase_words(const WordsArgs &a, int Q, hipStream_t s);
+// desc->next_sweep += sweeps[i] for every lattice of the series.
+hipError_t launch_advance_words(const WordsArgs &a, hipStream_t s);
+// int8 codes (row-major) <-> the 2-bit class layout, for L % 64 == 0.
+hipError_t launch_pack_int8(const int8_t *src, uint32_t *dst, int L, hipStream_t s);
+hipError_t launch_unpack_int8(const uint32_t *src, int8_t *dst, int L, hipStream_t s);
+
 // Launch shape of the 2-bit phase kernel: rows of the a-class per block
 // (0 = automatic) and blocks per compute unit.
 struct Tuning2Bit {
@@ -123,8 +161,12 @@ hipError_t launch_sweeps_2bit(const PhaseArgs &a, const Tuning2Bit &t, uint32_t 
 hipError_t launch_zero_i64(unsigned long long *p, int n, hipStream_t s);
 // Observable sums of the whole lattice into the observable slots (one block
 // per slot, at most kMaxObsSlots blocks), then the fold of slots into the
-// totals at scratch + kScrTrack (tracker) and + kScrObs (observables).
-hipError_t launch_observables(uint8_t *scratch, const void *state, int L, int encoding, hipStream_t s);
+// totals at scratch + kScrTrack (tracker) and + kScrObs (observables), or,
+// with a record, into record[0..9] (tracker, 7 sums) and record[10] = the
+// lattice's next sweep index (a series record, kSeriesRecord bytes).
+constexpr size_t kSeriesRecord = 88;
+hipError_t launch_observables(uint8_t *scratch, const void *state, int L, int encoding, hipStream_t s,
+                              long long *record = nullptr);
 // Batched kernel; dynamic LDS is sized for the largest L.  threads = block
 // size (a multiple of 64, at most 1024; 0 = min(1024, N/16 of the largest L)).
 // Map mode (section 3.2 random maps): lattices with L <= kMapMaxL, one block

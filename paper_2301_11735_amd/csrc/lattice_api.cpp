@@ -318,12 +318,19 @@ Schedule sweep_schedule(int32_t L, uint64_t seed, uint64_t s)
 namespace lat {
 namespace detail {
 
+namespace {
+
+// The buffer and encoding the off-chip kernels sweep: the lattice's own
+// state, or the 2-bit copy of a packed int8 lattice.
+void *swept_state(const lattice *h) { return h->packed ? (void *)(h->d_scratch + kScrWork) : h->d_state; }
+int swept_enc(const lattice *h) { return h->packed ? LAT_ENC_2BIT : h->enc; }
+
 // Host-scheduled path: four phase launches per sweep, then the device-side
 // sweep counter is advanced to match.
 int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
 {
     PhaseArgs a{};
-    a.state = h->d_state;
+    a.state = swept_state(h);
     a.dev_tab = (const uint2 *)(h->d_scratch + kScrDevTab);
     a.trans = (const uint2 *)(h->d_scratch + kScrTrans);
     a.trans_d = (const uint4 *)(h->d_scratch + kScrTransD);
@@ -331,8 +338,9 @@ int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
     a.L = h->L;
     a.key0 = (uint32_t)h->seed;
     a.key1 = (uint32_t)(h->seed >> 32);
+    const int enc = swept_enc(h);
     uint32_t left = sweeps;
-    if (h->enc == LAT_ENC_2BIT && h->tuning.persistent) {
+    if (enc == LAT_ENC_2BIT && h->tuning.persistent) {
         // one cooperative launch per chunk; the barrier counter stays far below 2^32
         constexpr uint32_t kChunk = 65536;
         while (left > 0) {
@@ -358,7 +366,7 @@ int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
             a.m = sc.m[p];
             a.k = sc.k[p];
             const hipError_t e =
-                h->enc == LAT_ENC_INT8 ? launch_phase_int8(a, stream) : launch_phase_2bit(a, h->tuning, stream);
+                enc == LAT_ENC_INT8 ? launch_phase_int8(a, stream) : launch_phase_2bit(a, h->tuning, stream);
             if (e != hipSuccess) return hip_fail(e, "phase kernel launch");
         }
     }
@@ -367,6 +375,84 @@ int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
         if (e != hipSuccess) return hip_fail(e, "advance kernel launch");
     }
     h->done += sweeps;
+    return LAT_OK;
+}
+
+// Multi-block word path: lattices in groups of up to kWordsBatch per launch,
+// one launch per phase of every sweep of the series (the lattice i of a
+// group skips the sweeps past sweeps[i]), then the device sweep counters
+// are advanced.  Q (lanes per a-word) is chosen by the largest L of the
+// group; every lattice's blocks must fit its kMaxSlots tracker slots.
+int enqueue_words_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps, uint32_t uniform,
+                         hipStream_t stream)
+{
+    for (int32_t b = 0; b < count; b += kWordsBatch) {
+        WordsArgs a{};
+        a.count = std::min<int32_t>(kWordsBatch, count - b);
+        int max_L = 0;
+        for (int i = 0; i < a.count; ++i) max_L = std::max(max_L, hs[b + i]->L);
+        const int Q = words_lanes(max_L);
+        uint32_t blocks = 0, most = 0;
+        for (int i = 0; i < a.count; ++i) {
+            const lattice *h = hs[b + i];
+            const uint32_t nb = words_blocks(h->L, Q);
+            if (nb > (uint32_t)kMaxSlots) return fail(LAT_EINVAL, "lattice too large for the multi-block word kernel");
+            a.scratch[i] = h->d_scratch;
+            a.sweeps[i] = sweeps ? sweeps[b + i] : uniform;
+            a.first_block[i] = blocks;
+            blocks += nb;
+            most = std::max(most, a.sweeps[i]);
+        }
+        a.first_block[a.count] = blocks;
+        if (most == 0) continue;
+        for (uint32_t it = 0; it < most; ++it) {
+            a.iter = it;
+            for (int p = 0; p < 4; ++p) {
+                a.p = p;
+                const hipError_t e = launch_phase_words(a, Q, stream);
+                if (e != hipSuccess) return hip_fail(e, "word phase kernel launch");
+            }
+        }
+        const hipError_t e = launch_advance_words(a, stream);
+        if (e != hipSuccess) return hip_fail(e, "advance kernel launch");
+        for (int i = 0; i < a.count; ++i) hs[b + i]->done += a.sweeps[i];
+    }
+    return LAT_OK;
+}
+
+}  // namespace
+
+int enqueue_offchip_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps, uint32_t uniform,
+                           hipStream_t stream, bool convert)
+{
+    auto n_of = [&](int32_t i) { return sweeps ? sweeps[i] : uniform; };
+    for (int32_t i = 0; i < count && convert; ++i) {
+        if (!hs[i]->packed || n_of(i) == 0) continue;
+        const hipError_t e = launch_pack_int8((const int8_t *)hs[i]->d_state,
+                                              (uint32_t *)(hs[i]->d_scratch + kScrWork), hs[i]->L, stream);
+        if (e != hipSuccess) return hip_fail(e, "int8 pack launch");
+    }
+    std::vector<lattice *> words;
+    std::vector<uint32_t> words_n;
+    for (int32_t i = 0; i < count; ++i) {
+        if (hs[i]->path == kPathWords) {
+            words.push_back(hs[i]);
+            words_n.push_back(n_of(i));
+        } else {
+            const int rc = enqueue_phase_sweeps(hs[i], n_of(i), stream);
+            if (rc) return rc;
+        }
+    }
+    if (!words.empty()) {
+        const int rc = enqueue_words_sweeps(words.data(), (int32_t)words.size(), words_n.data(), 0, stream);
+        if (rc) return rc;
+    }
+    for (int32_t i = 0; i < count && convert; ++i) {
+        if (!hs[i]->packed || n_of(i) == 0) continue;
+        const hipError_t e = launch_unpack_int8((const uint32_t *)(hs[i]->d_scratch + kScrWork),
+                                                (int8_t *)hs[i]->d_state, hs[i]->L, stream);
+        if (e != hipSuccess) return hip_fail(e, "int8 unpack launch");
+    }
     return LAT_OK;
 }
 
@@ -572,9 +658,36 @@ namespace {
 int enqueue_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
 {
     if (sweeps == 0) return LAT_OK;
-    if (h->phase_kernels) return enqueue_phase_sweeps(h, sweeps, stream);
     lattice *one[1] = {h};
-    return enqueue_lds_sweeps(one, 1, nullptr, sweeps, stream);
+    if (h->path != kPathLds) return enqueue_offchip_sweeps(one, 1, nullptr, sweeps, stream);
+    // a lone lattice is not autotuned (tuning synchronises); it takes the
+    // block size tuned for its shape by an earlier batch, else the default
+    return enqueue_lds_sweeps(one, 1, nullptr, sweeps, stream, /*tune=*/false);
+}
+
+// Sweep path of a new lattice.  Default: the one-block LDS kernel up to
+// kLdsRouteMaxL, whose single compute unit is then still faster than a
+// multi-block launch series; the multi-block word kernel up to kWordsMaxL;
+// the one-thread-per-word phase kernel above.  LATTICE_PATH=lds|words|phase
+// forces a path where it applies (tests run every path at small sizes);
+// LATTICE_FORCE_PHASE_KERNELS=1 is the same as LATTICE_PATH=phase.
+constexpr int kLdsRouteMaxL = 256;
+constexpr int kWordsMaxL = 2048;
+
+int choose_path(int L, int enc)
+{
+    const bool words_ok = L % 64 == 0 && L <= kWordsMaxL;
+    if (const char *v = std::getenv("LATTICE_PATH")) {
+        const std::string want(v);
+        if (want == "lds" && L <= kLdsMaxL) return kPathLds;
+        if (want == "words" && words_ok) return kPathWords;
+        if (want == "phase") return kPathPhase;
+    }
+    if (const char *force = std::getenv("LATTICE_FORCE_PHASE_KERNELS"))
+        if (std::atoi(force) != 0) return kPathPhase;
+    (void)enc;
+    if (L <= (L % 64 == 0 ? kLdsRouteMaxL : kLdsMaxL)) return kPathLds;
+    return words_ok ? kPathWords : kPathPhase;
 }
 
 }  // namespace
@@ -590,9 +703,8 @@ size_t lattice_state_bytes(int32_t L, int32_t encoding)
 
 size_t lattice_scratch_bytes(int32_t L, int32_t encoding)
 {
-    (void)L;
-    (void)encoding;
-    return kScrBytes;
+    if (!valid_geometry(L, encoding)) return kScrBytes;
+    return kScrBytes + (int8_packs(L, encoding) ? (size_t)L * L / 4 : 0);
 }
 
 int lattice_charge_target(int32_t L, double n, int64_t n_charged, int64_t *Q, int64_t *Nc)
@@ -657,10 +769,8 @@ int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void 
         h->d_scratch = (uint8_t *)d_scratch;
         h->stream = (hipStream_t)hip_stream;
         h->tuning = tuning_from_env();
-        {
-            const char *force = std::getenv("LATTICE_FORCE_PHASE_KERNELS");
-            h->phase_kernels = p->L > kLdsMaxL || (force && std::atoi(force) != 0);
-        }
+        h->path = choose_path(p->L, p->encoding);
+        h->packed = h->path != kPathLds && int8_packs(p->L, p->encoding);
         h->magic = kMagic;
         LatDesc desc{};
         desc.state = d_state;
@@ -718,16 +828,12 @@ int lattice_sweep_batch(lattice *const *hs, int32_t count, uint32_t sweeps, void
                 return fail(LAT_EINVAL, "a lattice appears twice in the batch");
         }
         if (sweeps == 0) return LAT_OK;
-        std::vector<lattice *> small;
-        for (int32_t i = 0; i < count; ++i) {
-            if (hs[i]->phase_kernels) {
-                const int rc = enqueue_phase_sweeps(hs[i], sweeps, (hipStream_t)hip_stream);
-                if (rc) return rc;
-            } else {
-                small.push_back(hs[i]);
-            }
-        }
-        return enqueue_lds_sweeps(small.data(), (int32_t)small.size(), nullptr, sweeps, (hipStream_t)hip_stream);
+        std::vector<lattice *> small, big;
+        for (int32_t i = 0; i < count; ++i) (hs[i]->path == kPathLds ? small : big).push_back(hs[i]);
+        int rc = enqueue_lds_sweeps(small.data(), (int32_t)small.size(), nullptr, sweeps, (hipStream_t)hip_stream);
+        if (rc == LAT_OK && !big.empty())
+            rc = enqueue_offchip_sweeps(big.data(), (int32_t)big.size(), nullptr, sweeps, (hipStream_t)hip_stream);
+        return rc;
     });
 }
 
@@ -749,7 +855,7 @@ int lattice_observables_batch(lattice *const *hs, int32_t count, void *d_out, si
         // lattices swept by the persistent kernel: its bounded device-wide
         // barrier flags a time-out in the lattice's error word
         for (int32_t i = 0; i < count && e == hipSuccess; ++i) {
-            if (!hs[i]->phase_kernels || !hs[i]->tuning.persistent) continue;
+            if (hs[i]->path != kPathPhase || !hs[i]->tuning.persistent) continue;
             uint32_t err = 0;
             e = hipMemcpy(&err, hs[i]->d_scratch + kScrErr, sizeof(err), hipMemcpyDeviceToHost);
             if (e == hipSuccess && (err & 1u))
@@ -757,6 +863,62 @@ int lattice_observables_batch(lattice *const *hs, int32_t count, void *d_out, si
         }
         if (e != hipSuccess) return hip_fail(e, "lattice_observables_batch");
         for (int32_t i = 0; i < count; ++i) fill_obs(hs[i], &v[10 * (size_t)i], &out[i]);
+        return LAT_OK;
+    });
+}
+
+int lattice_sweep_series(lattice *h, uint32_t intervals, uint32_t every, void *d_series, size_t series_bytes)
+{
+    return guarded("lattice_sweep_series", [&]() -> int {
+        if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
+        if (every == 0 || (intervals > 0 && !d_series)) return fail(LAT_EINVAL, "every must be > 0 and d_series set");
+        if (series_bytes / kSeriesRecord < intervals)
+            return fail(LAT_ENOMEM, "series buffer smaller than 88 bytes per interval");
+        if (intervals == 0) return LAT_OK;
+        lattice *one[1] = {h};
+        hipStream_t st = h->stream;
+        uint32_t *work = (uint32_t *)(h->d_scratch + kScrWork);
+        // a packed int8 lattice stays on its 2-bit copy for the whole series
+        if (h->packed) {
+            const hipError_t e = launch_pack_int8((const int8_t *)h->d_state, work, h->L, st);
+            if (e != hipSuccess) return hip_fail(e, "int8 pack launch");
+        }
+        for (uint32_t k = 0; k < intervals; ++k) {
+            const int rc = h->path == kPathLds ? enqueue_lds_sweeps(one, 1, nullptr, every, st, /*tune=*/false)
+                                               : enqueue_offchip_sweeps(one, 1, nullptr, every, st, /*convert=*/false);
+            if (rc) return rc;
+            long long *rec = (long long *)((uint8_t *)d_series + kSeriesRecord * (size_t)k);
+            const hipError_t e = launch_observables(h->d_scratch, h->packed ? (const void *)work : h->d_state, h->L,
+                                                    h->packed ? LAT_ENC_2BIT : h->enc, st, rec);
+            if (e != hipSuccess) return hip_fail(e, "observables launch");
+        }
+        if (h->packed) {
+            const hipError_t e = launch_unpack_int8(work, (int8_t *)h->d_state, h->L, st);
+            if (e != hipSuccess) return hip_fail(e, "int8 unpack launch");
+        }
+        return LAT_OK;
+    });
+}
+
+int lattice_series_read(lattice *h, const void *d_series, uint32_t intervals, lat_obs *out)
+{
+    return guarded("lattice_series_read", [&]() -> int {
+        if (!live(h)) return fail(LAT_ESTATE, "null or destroyed handle");
+        if (intervals > 0 && (!d_series || !out)) return fail(LAT_EINVAL, "null series or output");
+        if (intervals == 0) return LAT_OK;
+        std::vector<int64_t> v((size_t)intervals * (kSeriesRecord / 8));
+        uint32_t err = 0;
+        hipError_t e = hipMemcpyAsync(v.data(), d_series, v.size() * 8, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&err, h->d_scratch + kScrErr, sizeof(err), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(e, "lattice_series_read");
+        if (err & 1u) return fail(LAT_EHIP, "a device-wide phase barrier timed out; the state is invalid");
+        for (uint32_t k = 0; k < intervals; ++k) {
+            const int64_t *rec = &v[(kSeriesRecord / 8) * (size_t)k];
+            fill_obs(h, rec, &out[k]);
+            out[k].sweep = (uint64_t)rec[10] - h->start_sweep;
+        }
         return LAT_OK;
     });
 }

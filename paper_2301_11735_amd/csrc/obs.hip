@@ -72,8 +72,9 @@ __global__ void __launch_bounds__(1024) k_obs_2bit(const uint32_t *__restrict__ 
 }
 
 // Totals of one lattice: tracker = base triple + every tracker slot;
-// observables = the first n_obs observable slots.
-__global__ void __launch_bounds__(256) k_fold_sums(uint8_t *scr, int n_obs)
+// observables = the first n_obs observable slots.  Written to dst (tracker,
+// then the 7 sums) and, with stamp, dst[10] = the lattice's next sweep index.
+__global__ void __launch_bounds__(256) k_fold_sums(uint8_t *scr, int n_obs, long long *dst, int stamp)
 {
     long long t[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const long long *slots = (const long long *)(scr + kScrSlots);
@@ -92,7 +93,8 @@ __global__ void __launch_bounds__(256) k_fold_sums(uint8_t *scr, int n_obs)
     for (int i = threadIdx.x; i < n_obs; i += blockDim.x)
 #pragma unroll
         for (int k = 0; k < 7; ++k) t[3 + k] += os[7 * i + k];
-    block_reduce_store<10>(t, (long long *)(scr + kScrTrack));
+    block_reduce_store<10>(t, dst);
+    if (stamp && threadIdx.x == 0) dst[10] = (long long)((const LatDesc *)(scr + kScrDesc))->next_sweep;
 }
 
 }  // namespace
@@ -103,7 +105,8 @@ hipError_t launch_zero_i64(unsigned long long *p, int n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_observables(uint8_t *scratch, const void *state, int L, int encoding, hipStream_t s)
+hipError_t launch_observables(uint8_t *scratch, const void *state, int L, int encoding, hipStream_t s,
+                              long long *record)
 {
     const uint32_t units = encoding == 0 ? (uint32_t)L * L : (uint32_t)L * L / 16u;
     uint32_t grid = (units + 1023u) / 1024u;
@@ -115,7 +118,8 @@ hipError_t launch_observables(uint8_t *scratch, const void *state, int L, int en
         hipLaunchKernelGGL(k_obs_2bit, dim3(grid), dim3(1024), 0, s, (const uint32_t *)state, L, slots);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fold_sums, dim3(1), dim3(256), 0, s, scratch, (int)grid);
+    long long *dst = record ? record : (long long *)(scratch + kScrTrack);
+    hipLaunchKernelGGL(k_fold_sums, dim3(1), dim3(256), 0, s, scratch, (int)grid, dst, record ? 1 : 0);
     return hipGetLastError();
 }
 

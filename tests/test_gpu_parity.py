@@ -179,6 +179,7 @@ def test_large_config_invariants():
 @pytest.mark.parametrize("spec", [
     SMALL.with_(L=12, n=0.2, seed=61),
     SMALL.with_(L=32, seed=62),
+    SMALL.with_(L=128, seed=67),                                # int8 on its packed 2-bit copy
     SMALL.with_(L=100, Delta=-0.7, V=-0.3, T=1.7, seed=63),
     SMALL.with_(L=64, encoding=1, seed=64),
     SMALL.with_(L=192, encoding=1, T=0.5, seed=65),
@@ -188,6 +189,61 @@ def test_phase_kernel_path_matches_oracle(spec, monkeypatch):
     one-launch-per-phase kernels so both paths stay checked at small sizes."""
     monkeypatch.setenv("LATTICE_FORCE_PHASE_KERNELS", "1")
     _run_parity(spec, [1, 3, 10])
+
+
+@pytest.mark.parametrize("spec", [
+    SMALL.with_(L=64, encoding=1, seed=71),
+    SMALL.with_(L=128, encoding=0, n=-0.2, seed=72),                      # int8, swept on its 2-bit copy
+    SMALL.with_(L=192, encoding=1, Delta=0.9, V=-0.8, T=2.2, seed=73),    # 3 words per class row
+    SMALL.with_(L=576, encoding=0, T=0.6, seed=74),                       # int8, 9 words per class row
+    SMALL.with_(L=512, encoding=1, T=1.2, seed=75),
+    SMALL.with_(L=1024, encoding=1, n=0.3, T=0.4, seed=76),
+    SMALL.with_(L=2048, encoding=1, T=1.7, seed=77),
+], ids=lambda s: f"enc{s.encoding}-L{s.L}")
+def test_word_path_matches_oracle(spec, monkeypatch):
+    """The multi-block word kernel (Q lanes per a-word, schedules computed on
+    the device, several blocks per lattice) at every size it takes, both
+    encodings: the same chain as the oracle, bit for bit."""
+    monkeypatch.setenv("LATTICE_PATH", "words")
+    _run_parity(spec, [1, 3, 10] if spec.L <= 1024 else [1, 2])
+
+
+@pytest.mark.parametrize("spec", [
+    SMALL.with_(L=64, encoding=0, seed=78),
+    SMALL.with_(L=4096, encoding=0, T=1.1, seed=79),
+], ids=lambda s: f"L{s.L}")
+def test_packed_int8_on_the_phase_kernel_matches_oracle(spec, monkeypatch):
+    """Int8 lattices on the one-thread-per-word phase kernel run on a 2-bit
+    copy packed before and unpacked after each call (L = 4096 takes that path
+    by default)."""
+    if spec.L <= 1024:
+        monkeypatch.setenv("LATTICE_PATH", "phase")
+    _run_parity(spec, [1, 3] if spec.L > 1024 else [1, 3, 10])
+
+
+def test_mixed_paths_in_one_batch_match_oracle():
+    """One lattice_sweep_batch over lattices on all three paths (on-chip,
+    multi-block word kernel in one batched launch series, phase kernel):
+    every lattice bit-exact against its own oracle run."""
+    _say("case mixed paths")
+    rng = np.random.default_rng(9)
+    specs = []
+    for i, (L, enc) in enumerate([(64, 1), (100, 0), (320, 1), (512, 0), (576, 1), (1024, 1), (516, 0)]):
+        specs.append(SMALL.with_(L=L, encoding=enc, seed=1500 + i, n=float(rng.uniform(-0.3, 0.3)),
+                                 Delta=float(rng.uniform(-1, 1)), V=float(rng.uniform(-1, 1)),
+                                 T=float(rng.uniform(0.2, 2.5))))
+    gs = [_make(s) for s in specs]
+    os_ = [_oracle(s) for s in specs]
+    obs = lat.BatchObservables(len(gs))
+    for k in (4, 3):
+        lat.sweep_batch(gs, k)
+        for o in os_:
+            o.sweeps(k)
+        got = obs(gs)
+        for s, g, o, go in zip(specs, gs, os_, got):
+            assert np.array_equal(g.read_state(), o.codes), f"L={s.L} enc={s.encoding}"
+            assert go.ints() == o.observables().tolist()
+            assert [go.track_nD, go.track_nV, go.track_nJ] == o.track.tolist()
 
 
 @pytest.mark.parametrize("rows,bpc", [(1, 1), (2, 4), (32, 1), (8, 2)])
@@ -430,3 +486,29 @@ def test_batch_graph_replays_match_eager_and_oracle(kind, threads, monkeypatch):
     for g, o in zip(glats, os_):
         o.sweeps(3)
         assert np.array_equal(g.read_state(), o.codes)
+
+
+@pytest.mark.parametrize("spec,every,intervals", [
+    (workloads.MID, 1, 12),                                        # int8 L=1024 on its 2-bit copy, every sweep
+    (SMALL.with_(L=64, encoding=1, seed=91), 3, 8),                # on-chip path
+    (SMALL.with_(L=4096, encoding=0, T=1.1, seed=92), 1, 3),       # phase kernel, packed int8
+    (SMALL.with_(L=100, seed=93), 2, 5),                           # int8 with L % 64 != 0
+], ids=["mid", "lds", "phase-int8", "int8-L100"])
+def test_device_observation_series_matches_oracle(spec, every, intervals):
+    """lattice_sweep_series keeps the observables of every interval on the
+    device (no host synchronisation between intervals); each record equals the
+    oracle's observables, tracker and sweep count after that interval, and
+    the state after the series is the oracle's."""
+    _say(f"case series L={spec.L} enc={spec.encoding} every={every} intervals={intervals}")
+    g, o = _pair(spec)
+    g.sweep(2)
+    o.sweeps(2)
+    recs = g.sweep_series(intervals, every)
+    for k, r in enumerate(recs):
+        o.sweeps(every)
+        assert r.ints() == o.observables().tolist(), k
+        assert [r.track_nD, r.track_nV, r.track_nJ] == o.track.tolist(), k
+        assert r.sweep == 2 + every * (k + 1)
+        assert r.E == o.energy()
+    _assert_same(g, o, "after the series")
+    g.destroy()
