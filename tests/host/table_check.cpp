@@ -16,7 +16,12 @@ namespace lat {
 hipError_t launch_phase_int8(const PhaseArgs &, hipStream_t) { return hipSuccess; }
 hipError_t launch_phase_2bit(const PhaseArgs &, const Tuning2Bit &, hipStream_t) { return hipSuccess; }
 hipError_t launch_zero_i64(unsigned long long *, int, hipStream_t) { return hipSuccess; }
-hipError_t launch_observables(uint8_t *, const void *, int, int, hipStream_t) { return hipSuccess; }
+hipError_t launch_observables(uint8_t *, const void *, int, int, hipStream_t, long long *) { return hipSuccess; }
+int words_lanes(int) { return 1; }
+hipError_t launch_phase_words(const WordsArgs &, int, hipStream_t) { return hipSuccess; }
+hipError_t launch_advance_words(const WordsArgs &, hipStream_t) { return hipSuccess; }
+hipError_t launch_pack_int8(const int8_t *, uint32_t *, int, hipStream_t) { return hipSuccess; }
+hipError_t launch_unpack_int8(const uint32_t *, int8_t *, int, hipStream_t) { return hipSuccess; }
 hipError_t launch_sweep_lds(const BatchArgs &, int, int, bool, hipStream_t) { return hipSuccess; }
 hipError_t init_kernel_attributes() { return hipSuccess; }
 hipError_t init_map_kernel_attributes() { return hipSuccess; }
