@@ -163,6 +163,20 @@ int lattice_sweep_batch(lattice *const *hs, int32_t count, uint32_t sweeps, void
 int lattice_observables_batch(lattice *const *hs, int32_t count, void *d_out, size_t out_bytes, lat_obs *out,
                               void *hip_stream);
 
+/* lattice_observables_batch for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation): the same records, with the device staging taken from a
+ * static array inside the library instead of a caller buffer.  The array
+ * holds 1024 records (80 KiB) on each device the library runs on, for the
+ * life of the process; the current device of the calling thread must be the
+ * lattices' device.  The call allocates no device memory and keeps its host
+ * staging on the stack.  Every call on a device shares that device's array:
+ * calls that overlap on one device (other threads, other streams) race and
+ * must be serialised by the caller.  Synchronises hip_stream.
+ * Errors: LAT_EINVAL (count < 0 or > 1024, null pointers), LAT_ESTATE,
+ * LAT_EHIP. */
+int lattice_observables_batch_noalloc(lattice *const *hs, int32_t count, lat_obs *out, void *hip_stream);
+
 /* Batched observation intervals captured once into a HIP graph (section 3.2,
  * lattice copies advanced together).  One replay runs `intervals` intervals;
  * each advances the `count` lattices by `sweeps` sweeps and reduces their

@@ -30,6 +30,7 @@ EXPORTS = (
     "lattice_series_read",
     "lattice_sweep_batch",
     "lattice_observables_batch",
+    "lattice_observables_batch_noalloc",
     "lattice_batch_graph_create",
     "lattice_batch_graph_launch",
     "lattice_batch_graph_read",
@@ -155,6 +156,8 @@ def lib() -> ctypes.CDLL:
         L.lattice_sweep_batch.restype = ctypes.c_int
         L.lattice_observables_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, vp, sz, ctypes.POINTER(LatObs), vp]
         L.lattice_observables_batch.restype = ctypes.c_int
+        L.lattice_observables_batch_noalloc.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(LatObs), vp]
+        L.lattice_observables_batch_noalloc.restype = ctypes.c_int
         L.lattice_batch_graph_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint32,
                                                  vp, sz, vp, ctypes.POINTER(vp)]
         L.lattice_batch_graph_create.restype = ctypes.c_int
@@ -354,6 +357,15 @@ class BatchObservables:
         _check(lib().lattice_observables_batch(_handles(lattices), n, self.buf.data_ptr(), self.buf.numel(), out,
                                                _stream_handle(stream)))
         return list(out)[:n]
+
+
+def observables_batch_noalloc(lattices, stream=None) -> list:
+    """Observables of up to 1024 lattices (as BatchObservables) with the
+    library's static device staging: no device buffer is allocated."""
+    n = len(lattices)
+    out = (LatObs * max(1, n))()
+    _check(lib().lattice_observables_batch_noalloc(_handles(lattices), n, out, _stream_handle(stream)))
+    return list(out)[:n]
 
 
 class BatchGraph:

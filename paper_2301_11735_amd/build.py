@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblattice.so")
 SOURCES = [os.path.join(CSRC, n) for n in ("lattice_api.cpp", "server.cpp", "graph.cpp", "maps.cpp", "penalty.cpp", "phase.hip", "obs.hip", "batch.hip", "words.hip",
-                                              "maps.hip", "penalty.hip")]
+                                              "maps.hip", "penalty.hip", "noalloc.hip")]
 ARCH = os.environ.get("LATTICE_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
