@@ -6,12 +6,13 @@ launches each) followed by the grid-wide observable reduction.  The lattice is
 created (init, threshold table) before the timed region, so its inputs are
 resident in HBM when timing starts.
 
-The same line also carries the batched workload (256 lattices of L = 128,
-lattices/s) and a short served run (Poisson arrivals, p50/p99 time-to-result),
-the other two parts of the metric.
+The same line also carries the single mid lattice (L = 1024 int8, observables
+after every sweep), the batched workload (256 lattices of L = 128,
+lattices/s) and the served stream (Poisson arrivals, p50/p99
+time-to-result), the other parts of the metric.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--no-batched] [--serve-seconds S]
+                       [--no-batched] [--no-mid] [--serve-seconds S]
 """
 from __future__ import annotations
 
@@ -28,20 +29,23 @@ if ROOT not in sys.path:
 import workloads  # noqa: E402
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 full-rate 32-bit
-# integer VALU lane-operations per second.
+# integer VALU lane-operations per second; 1024 SIMDs issue one wave64 VALU
+# instruction per 4 cycles each.
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
+N_SIMD, CLOCK_HZ = 1024, 2.4e9
 HBM_PEAK_GBS = 8000.0
-# Algorithmic integer work per site update that the method fixes: half a
-# Philox4x32-10 call per pair, i.e. a quarter call per site update.  A call is
-# 10 rounds of two 32x32->64 multiplies (v_mad_u64_u32) and two three-input
-# xors (v_bitop3_b32), all full-rate on gfx950: 40 lane-ops per call.  Only
-# this RNG floor is counted, so the fraction is a lower bound on ALU use.
-ALU_OPS_PER_SITE_UPDATE = 10.0
-# Algorithmic HBM bytes per site update at 2 bits per site: read + write once.
+# Algorithmic HBM bytes per site update at 2 bits per site: the state read and
+# written once, 0.5 B (the roofline's per-unit figure).
 BYTES_PER_SITE_UPDATE_2BIT = 0.5
+# The RNG floor of the method's integer work: half a Philox4x32-10 call per
+# pair, i.e. a quarter call per site update; a call is 10 rounds of two
+# 32x32->64 multiplies and two three-input xors, all full-rate on gfx950, so
+# 40 lane-ops per call.  Reported only as a lower bound on ALU use.
+PHILOX_OPS_PER_SITE_UPDATE = 10.0
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_phase_2bit_L8192_traffic.txt")
+VALU_SUMMARY = os.path.join(ROOT, "profiles", "k_phase_2bit_L8192_valu.txt")
 
 
 PHASE_KERNEL_SOURCES = ("phase.hip", "device_common.h", "kernels.h", "philox.h")
@@ -57,22 +61,62 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per phase launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary, or None if it was taken on another kernel source."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+def _summary_values(path):
+    """key = value lines of a committed counter summary, or None if it is
+    missing or was taken on another phase-kernel source."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_SUMMARY):
+    for line in open(path):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
     if vals.get("phase_sources_sha256") != kernel_source_digest():
         return None
+    return vals
+
+
+def measured_traffic():
+    """HBM bytes per phase launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None if it was taken on another kernel source."""
+    vals = _summary_values(TRAFFIC_SUMMARY)
     try:
         return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
-    except (KeyError, ValueError):
+    except (TypeError, KeyError, ValueError):
         return None
+
+
+def measured_valu_insts():
+    """VALU wave-instructions per phase launch (rocprofv3 SQ_INSTS_VALU) from
+    the committed summary, or None if it was taken on another kernel source."""
+    vals = _summary_values(VALU_SUMMARY)
+    try:
+        return float(vals["valu_insts_per_launch"])
+    except (TypeError, KeyError, ValueError):
+        return None
+
+
+def write_valu_summary(csv_path, out=VALU_SUMMARY):
+    """Mean SQ_INSTS_VALU of the L=8192 phase kernel per dispatch, keyed to
+    the digest of its sources."""
+    import statistics
+
+    v = [x for k, x in _counter_rows(csv_path) if "k_phase_2bit" in k]
+    n_updates = workloads.LARGE.L ** 2 / 4
+    lines = [
+        "# VALU wave-instructions of k_phase_2bit at L=8192 (one phase launch updates N/4 = 16.8M sites)",
+        "# counter: rocprofv3 --pmc SQ_INSTS_VALU on",
+        "#   python3 bench.py --steps 4 --warmup 1 --no-cpu-baseline --no-batched --no-mid --no-maps --no-penalty"
+        " --serve-seconds 0",
+        "# written by: python3 bench.py --valu-summary <counter csv>",
+        f"# phase dispatches: {len(v)}; mean {statistics.mean(v):.1f} min {min(v):.1f} max {max(v):.1f}",
+        f"# lane-ops per site update (x64 lanes / N/4): {statistics.mean(v) * 64 / n_updates:.2f}",
+        f"# phase_sources_sha256 covers csrc/{', csrc/'.join(PHASE_KERNEL_SOURCES)}",
+        f"phase_sources_sha256={kernel_source_digest()}",
+        f"valu_insts_per_launch={statistics.mean(v):.0f}",
+    ]
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def _counter_rows(path):
@@ -168,24 +212,42 @@ def write_counter_summary(out_md, csvs, trace_stats=None):
     print("\n".join(lines))
 
 
+def _progress(msg: str):
+    """One line on stderr per finished leg (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--cpu-sweeps", type=int, default=20)
+    ap.add_argument("--cpu-all-cores-sweeps", type=int, default=600,
+                    help="sweeps per lattice of the batched workload in the all-cores oracle run (0 skips it)")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-mid", action="store_true")
     ap.add_argument("--no-maps", action="store_true")
     ap.add_argument("--no-penalty", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=10.0, help="0 skips the served run")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="0 skips the served run")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only copy a device buffer of this many MiB 3 times (HBM counter calibration) and exit")
     ap.add_argument("--counter-summary", nargs="+", metavar=("OUT_MD", "CSV"),
                     help="write per-kernel means of rocprofv3 --pmc counter_collection.csv files to OUT_MD and exit")
+    ap.add_argument("--valu-summary", metavar="CSV",
+                    help="write the VALU summary from a rocprofv3 --pmc SQ_INSTS_VALU counter_collection.csv and exit")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="write the traffic summary from four rocprofv3 --pmc counter_collection.csv files and exit")
     return ap.parse_args()
+
+
+def host_cores() -> int:
+    """Cores this process may run on (the affinity mask, else the count)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
 
 def cpu_baseline(spec: workloads.LatticeSpec, sweeps: int) -> dict:
@@ -201,8 +263,36 @@ def cpu_baseline(spec: workloads.LatticeSpec, sweeps: int) -> dict:
         "value": spec.L * spec.L * sweeps / dt,
         "unit": "site updates/s",
         "cores": 1,
+        "host_cores": host_cores(),
         "kind": "oracle",
         "sample": f"{sweeps} sweeps of the L={spec.L} lattice (same parameters and seed), init not timed",
+    }
+
+
+def cpu_all_cores(sweeps: int, workers: int) -> dict:
+    """The unmodified sequential oracle on every host core at once: the
+    batched workload's 256 lattices, one lattice per worker thread at a time
+    (the oracle's C sweeps run outside the Python lock), `sweeps` sweeps each;
+    init not timed."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    specs = workloads.batched_specs()
+    lats = [oracle.OracleLattice(s.L, s.n, s.Delta, s.V, s.J, s.T, s.seed) for s in specs]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(lambda o: o.sweeps(sweeps), lats))
+    dt = time.perf_counter() - t0
+    updates = sum(s.L * s.L for s in specs) * sweeps
+    return {
+        "value": updates / dt,
+        "unit": "site updates/s",
+        "cores": workers,
+        "kind": "oracle",
+        "sample": f"the batched workload's 256 L=128 lattices, {sweeps} of their 5000 sweeps each, "
+                  f"one sequential oracle run per core",
+        "lattices_per_s_equivalent": updates / dt / (specs[0].L ** 2 * specs[0].sweeps),
     }
 
 
@@ -290,6 +380,37 @@ def batched_run(torch, lat, b2b_sample: int = 8, b2b_sweeps: int = 1000) -> dict
     return out
 
 
+def mid_run(torch, lat) -> dict:
+    """The single mid lattice: L=1024 int8 (seed 2), 2000 sweeps with the
+    observables after every sweep, run as one device-side observation series
+    (per interval the sweep's phase launches, then the observable reduction
+    into that interval's record; the 2000 records are read back once at the
+    end).  Creation and a warm-up on a throw-away lattice are not timed."""
+    s = workloads.MID
+    warm = lat.Lattice(s.L, s.n, s.Delta, s.V, s.J, s.T, s.seed, encoding=s.encoding)
+    warm.sweep_series(20, s.every)
+    warm.destroy()
+    g = lat.Lattice(s.L, s.n, s.Delta, s.V, s.J, s.T, s.seed, encoding=s.encoding)
+    o0 = g.observables()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    buf = g.sweep_series(s.sweeps // s.every, s.every, read=False)
+    recs = g.read_series(buf, s.sweeps // s.every)  # synchronises
+    dt = time.perf_counter() - t0
+    Q, _ = lat.charge_target(s.L, s.n)
+    assert all(r.sum_S == Q for r in recs), "charge constraint violated"
+    assert recs[-1].sweep == s.sweeps
+    assert recs[-1].track_nD == recs[-1].n_charged - o0.n_charged, "tracker drifted from the recomputed energy"
+    g.destroy()
+    return {
+        "workload": f"single mid lattice L={s.L} int8, J=1 V=0.5 Delta=0 T=1 n=0.05 seed {s.seed}, "
+                    f"{s.sweeps} sweeps, observables after every sweep (device-side series, read once)",
+        "site_updates_per_s": s.L * s.L * s.sweeps / dt,
+        "ms_per_sweep": 1e3 * dt / s.sweeps,
+        "seconds": dt,
+    }
+
+
 def map_run(torch, lat, n_maps: int = 100) -> dict:
     """Map mode (the paper's random maps, built on the device) on the batched
     workload's 256 lattices of L=128: n_maps maps each in one launch."""
@@ -355,6 +476,9 @@ def main():
     if args.traffic_summary:
         write_traffic_summary(*args.traffic_summary)
         return
+    if args.valu_summary:
+        write_valu_summary(args.valu_summary)
+        return
     if args.counter_summary:
         out_md, *rest = args.counter_summary
         us = os.environ.get("PHASE_KERNEL_TRACE_US")
@@ -412,7 +536,9 @@ def main():
     phase_us = sweep_ms * 1e3 / (args.steps * every * 4)
     value = N * every * args.steps / wall
     per_launch_updates = N / 4  # one phase updates N/8 pairs
-    alu_achieved = per_launch_updates * ALU_OPS_PER_SITE_UPDATE / (phase_us * 1e-6)
+    algo_bytes = per_launch_updates * BYTES_PER_SITE_UPDATE_2BIT
+    hbm_achieved = algo_bytes / (phase_us * 1e-6) / 1e9
+    valu_insts = measured_valu_insts()
 
     last = obs[-1]
     Q, _ = lat.charge_target(spec.L, spec.n)
@@ -440,31 +566,48 @@ def main():
             "encoding": "2bit",
         },
         "roofline": {
-            "bound": "alu",
-            "achieved": alu_achieved / 1e12,
-            "peak": VALU_PEAK_OPS / 1e12,
-            "unit": "Tops/s",
-            "frac": alu_achieved / VALU_PEAK_OPS,
+            "bound": "hbm",
+            "achieved": hbm_achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": hbm_achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(),
             "kernel": "k_phase_2bit",
             "avg_launch_us": phase_us,
-        },
-        "hbm_effective": {
-            "GB_per_s": value * BYTES_PER_SITE_UPDATE_2BIT / 1e9,
-            "frac_of_peak": value * BYTES_PER_SITE_UPDATE_2BIT / 1e9 / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_launch": algo_bytes,
+            # what binds the kernel: VALU issue (SQ_INSTS_VALU of the committed
+            # counter summary over the live launch time)
+            "valu": {
+                "issue_frac": valu_insts * 4 / (N_SIMD * phase_us * 1e-6 * CLOCK_HZ) if valu_insts else None,
+                "lane_ops_per_site_update": valu_insts * 64 / per_launch_updates if valu_insts else None,
+                "philox_floor_frac_lower_bound":
+                    per_launch_updates * PHILOX_OPS_PER_SITE_UPDATE / (phase_us * 1e-6) / VALU_PEAK_OPS,
+            },
         },
     }
     g.destroy()
+    _progress(f"large lattice: {value:.4g} site updates/s, phase {phase_us:.2f} us")
+    if not args.no_mid:
+        line["mid"] = mid_run(torch, lat)
+        _progress(f"mid lattice: {line['mid']['site_updates_per_s']:.4g} site updates/s")
     if not args.no_batched:
         line["batched"] = batched_run(torch, lat)
+        _progress(f"batched: {line['batched']['lattices_per_s']:.5g} lattices/s")
     if not args.no_maps:
         line["map_mode"] = map_run(torch, lat)
+        _progress("map mode done")
     if not args.no_penalty:
         line["penalty_mode"] = penalty_run(torch, lat)
+        _progress("penalty mode done")
     if args.serve_seconds > 0:
         line["served"] = served_run(args.serve_seconds)
+        _progress(f"served: p50 {line['served']['p50_s']:.3f} s, p99 {line['served']['p99_s']:.3f} s")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec, args.cpu_sweeps)
+        _progress(f"cpu baseline: {line['cpu_baseline']['value']:.4g} site updates/s on 1 core")
+        if args.cpu_all_cores_sweeps > 0:
+            # the machine's CPU share per GPU is 16 cores, whatever the host reports
+            line["cpu_baseline"]["all_cores"] = cpu_all_cores(args.cpu_all_cores_sweeps, min(16, host_cores()))
     print(json.dumps(line), flush=True)
 
 

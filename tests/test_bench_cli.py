@@ -47,3 +47,15 @@ def test_traffic_summary_scales_by_the_copy(tmp_path, monkeypatch):
     assert bench.measured_traffic() == 200 * 2048 + 50 * 1024
     out.write_text(out.read_text().replace(bench.kernel_source_digest(), "0" * 64))
     assert bench.measured_traffic() is None
+
+
+def test_valu_summary_is_keyed_to_the_kernel_sources(tmp_path, monkeypatch):
+    phase = "void lat::(anonymous namespace)::k_phase_2bit<1>(lat::PhaseArgs, int)"
+    _csv(tmp_path / "v.csv", [(phase, "SQ_INSTS_VALU", 7.0e6), (phase, "SQ_INSTS_VALU", 7.2e6),
+                              ("k_obs_2bit", "SQ_INSTS_VALU", 1.0)])
+    out = tmp_path / "valu.txt"
+    bench.write_valu_summary(str(tmp_path / "v.csv"), out=str(out))
+    monkeypatch.setattr(bench, "VALU_SUMMARY", str(out))
+    assert bench.measured_valu_insts() == 7.1e6
+    out.write_text(out.read_text().replace(bench.kernel_source_digest(), "0" * 64))
+    assert bench.measured_valu_insts() is None
