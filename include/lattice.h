@@ -208,13 +208,19 @@ int lattice_batch_graph_destroy(lat_batch_graph *g);
  * Serving: simulation requests that arrive while others run.  The server
  * admits queued requests, in arrival order, into the caller's device pool when
  * a slot and pool memory are free; every call of lat_server_step advances all
- * resident requests together in one batched launch (section 3.2: lattice
- * copies processed together), each by about the same time on its compute
- * unit: max(1, quantum_updates / (N + 11000)) sweeps, capped by what the
- * request still needs (a sweep costs about N + 11000 site-update times, the
- * constant being its fixed per-phase cost), then harvests the finished ones
- * and frees their memory, so new
- * requests join between steps.  A request's result is bit-identical to
+ * resident requests together (section 3.2: lattice copies processed
+ * together), then harvests the finished ones and frees their memory, so new
+ * requests join between steps.  Lattices that fit one compute unit's on-chip
+ * memory by default (L <= 256, or L % 64 != 0) share one batched launch on
+ * the server's stream, each by about the same time on its compute unit:
+ * max(1, quantum_updates / (N + 11000)) sweeps, capped by what the request
+ * still needs (a sweep costs about N + 11000 site-update times, the constant
+ * being its fixed per-phase cost).  The others (L = 320 .. 512, L % 64 == 0)
+ * advance on a second stream of the server at its own pace, spread over many
+ * compute units (one launch per phase holds all of them): while fewer than
+ * two of its chunks are in flight, a step queues one more, of
+ * max(1, quantum_updates / 100000) sweeps of each of them, and they are
+ * harvested once the chunk holding their last sweep has completed.  A request's result is bit-identical to
  * running it alone with lattice_create/lattice_sweep.  Served lattices need
  * L <= 512.  Timestamps are seconds of the monotonic clock (CLOCK_MONOTONIC).
  */

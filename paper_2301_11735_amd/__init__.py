@@ -131,6 +131,10 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2301_11735_amd/build.py")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded, so that one runtime serves both in this process
+        import torch  # noqa: F401
+
         L = ctypes.CDLL(LIB_PATH)
         vp, sz = ctypes.c_void_p, ctypes.c_size_t
         L.lattice_state_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]

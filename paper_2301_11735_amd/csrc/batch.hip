@@ -225,33 +225,8 @@ __device__ __forceinline__ void word_sweeps(uint32_t *lat, uint32_t *sched, cons
 // class layout, read from st (global memory or the LDS copy).
 __device__ __forceinline__ void obs_sums_2bit(const uint32_t *st, int L, long long (&v)[7])
 {
-    const int W = L >> 6, H = L >> 1, Lq = L >> 2;
-    const uint32_t csz = (uint32_t)H * W;
-    for (uint32_t i = threadIdx.x; i < 8u * csz; i += blockDim.x) {
-        const int c = (int)(i / csz);
-        const uint32_t rem = i - (uint32_t)c * csz;
-        const int Y = (int)(rem / W), j = (int)(rem - (uint32_t)Y * W);
-        const int cx = c & 3, cy = c >> 2;
-        const uint32_t w = st[i];
-        const uint32_t wr = cx < 3 ? st[i + csz]
-                                   : load16(st, (uint32_t)(4 * cy) * csz + (uint32_t)Y * W, W,
-                                            16 * j + 1 == Lq ? 0 : 16 * j + 1);
-        const uint32_t wd = cy == 0 ? st[i + 4 * csz] : st[(uint32_t)cx * csz + (uint32_t)(Y + 1 == H ? 0 : Y + 1) * W + j];
-        const uint32_t h = (w >> 1) & kM5, l = w & kM5;
-        const int sumS = __popc(h & ~l) - __popc(h & l);
-        const int sumG = __popc((h | l) ^ kM5) - __popc(l & ~h);
-        int bSS = 0, bss = 0;
-        bond_sums(h, l, (wr >> 1) & kM5, wr & kM5, bSS, bss);
-        bond_sums(h, l, (wd >> 1) & kM5, wd & kM5, bSS, bss);
-        const int sg = ((cx + cy) & 1) ? -1 : 1;
-        v[0] += sumS;
-        v[1] += __popc(h);
-        v[2] += bSS;
-        v[3] += bss;
-        v[4] += sumG;
-        v[5] += sg * sumG;
-        v[6] += sg * sumS;
-    }
+    const uint32_t n = 8u * (uint32_t)(L >> 1) * (uint32_t)(L >> 6);
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) obs_word_2bit(st, L, i, v);
 }
 
 // This thread's share of a lattice's tracker slots (phase kernels) and, for

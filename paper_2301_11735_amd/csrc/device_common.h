@@ -226,6 +226,33 @@ __device__ __forceinline__ void device_schedule(int L, uint32_t k0, uint32_t k1,
     }
 }
 
+// Device-wide barrier between phases of the persistent kernels: every block
+// arrives once per phase on a monotonic counter.  Release: every wave fences
+// (a wave's fence waits only for its own stores and atomics), so the block's
+// results are past the compute unit's caches before its arrival; acquire:
+// the fence after the wait invalidates the caches the block reads through.
+// The wait is bounded: after about 2^24 polls the block raises the error
+// flag and goes on (results are then invalid and reported as an error), so
+// no wave can spin forever.
+__device__ __forceinline__ void grid_barrier(unsigned *counter, unsigned target, unsigned *err)
+{
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(counter, 1u);
+        unsigned polls = 0;
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++polls > (1u << 24)) {
+                atomicOr(err, 1u);
+                break;
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
 // Word i of an array below 4 GiB (every lattice state is): a 32-bit byte
 // offset from the base, so that a uniform base stays in scalar registers and
 // no 64-bit address is formed per access.

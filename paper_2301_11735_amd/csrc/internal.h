@@ -33,6 +33,11 @@ struct lattice {
     lat::Tuning2Bit tuning{0, 0, 0, 0};
     int path = kPathLds;
     bool packed = false;  // int8 swept on the 2-bit copy at scratch + kScrWork
+    // persistent multi-block launches (kPathWords): blocks per launch, 0 when
+    // unavailable, -1 before the first look-up; set once one has run, so that
+    // reads check the barrier's time-out flag
+    int series_grid = -1;
+    bool ran_persistent = false;
     uint32_t magic = 0;
 };
 
@@ -78,9 +83,21 @@ int enqueue_observables_batch(lattice *const *hs, int32_t count, unsigned long l
 // convert = false: packed lattices are already on (and stay on) their copy.
 int enqueue_offchip_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps, uint32_t uniform,
                            hipStream_t stream, bool convert = true);
+// Sweeps (and, with records, an observation series: intervals x every sweeps,
+// a kSeriesRecord record after each interval) of one lattice on the
+// multi-block path as persistent launches.  *ran = false (nothing enqueued)
+// when the persistent form is off (by default above L = 512;
+// LATTICE_WORDS_PERSISTENT=0|1 overrides) or cannot be launched here; the
+// caller then uses the per-phase launches.  The lattice
+// must already be on its 2-bit copy if it is a packed int8 lattice.
+int enqueue_words_persistent(lattice *h, uint32_t intervals, uint32_t every, long long *records, hipStream_t stream,
+                             bool *ran);
 // Checks of lat_params (geometry, finite couplings, T > 0, the charge target
 // of eq. 2); writes the target charge and the charged count.
 int validate_params(const lat_params *p, int64_t *Q, int64_t *Nc);
+// The lattice has run a persistent kernel, whose bounded device-wide barrier
+// flags a time-out in its error word.
+bool barrier_may_time_out(const lattice *h);
 // v = (tracker nD, nV, nJ, sum S, sum S^2, bonds SS, bonds ss, M, M_st, C_st).
 void fill_obs(const lattice *h, const int64_t *v, lat_obs *out);
 

@@ -422,6 +422,55 @@ int enqueue_words_sweeps(lattice *const *hs, int32_t count, const uint32_t *swee
 
 }  // namespace
 
+constexpr int kWordsPersistentMaxL = 512;
+
+int enqueue_words_persistent(lattice *h, uint32_t intervals, uint32_t every, long long *records, hipStream_t stream,
+                             bool *ran)
+{
+    *ran = false;
+    if (h->path != kPathWords || intervals == 0 || every == 0) return LAT_OK;
+    // default: on up to L = 512, where it measured faster than one launch per
+    // phase (13.6 against 21.9 us a sweep at L = 512); above, its
+    // device-coherent loads, which bypass the L2, cost more than the launches
+    // they save (27 against 24 us at L = 1024).  LATTICE_WORDS_PERSISTENT=0|1
+    // overrides.
+    const char *v = std::getenv("LATTICE_WORDS_PERSISTENT");
+    if (v ? std::atoi(v) == 0 : h->L > kWordsPersistentMaxL) return LAT_OK;
+    const int Q = words_lanes(h->L);
+    if (h->series_grid < 0) h->series_grid = words_series_grid(h->L, Q);
+    if (h->series_grid <= 0) return LAT_OK;
+    // the barrier counter counts blocks x barriers: at most 2^20 barriers per
+    // launch keeps it far below 2^32
+    constexpr uint64_t kMaxBarriers = 1u << 20;
+    const uint64_t per_interval = 4ull * every + (records ? 1u : 0u);
+    if (per_interval > kMaxBarriers) {
+        if (records) return LAT_OK;  // such long intervals take the per-phase launches
+        // plain sweeps: split into launches of at most 2^18 sweeps
+        uint32_t left = every;
+        while (left > 0) {
+            const uint32_t n = std::min<uint32_t>(left, kMaxBarriers / 4);
+            const int rc = enqueue_words_persistent(h, 1, n, nullptr, stream, ran);
+            if (rc || !*ran) return rc;
+            left -= n;
+        }
+        return LAT_OK;
+    }
+    const uint32_t chunk = (uint32_t)std::min<uint64_t>(intervals, kMaxBarriers / per_interval);
+    for (uint32_t k = 0; k < intervals; k += chunk) {
+        WordsSeriesArgs a{};
+        a.scratch = h->d_scratch;
+        a.intervals = std::min(chunk, intervals - k);
+        a.every = every;
+        a.records = records ? records + (kSeriesRecord / 8) * (size_t)k : nullptr;
+        const hipError_t e = launch_words_series(a, Q, h->series_grid, stream);
+        if (e != hipSuccess) return hip_fail(e, "persistent word kernel launch");
+        h->done += (uint64_t)a.intervals * every;
+    }
+    h->ran_persistent = true;
+    *ran = true;
+    return LAT_OK;
+}
+
 int enqueue_offchip_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps, uint32_t uniform,
                            hipStream_t stream, bool convert)
 {
@@ -605,6 +654,11 @@ int enqueue_lds_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps
 }
 
 // v = (tracker nD, nV, nJ, sum S, sum S^2, bonds SS, bonds ss, M, M_st, C_st).
+bool barrier_may_time_out(const lattice *h)
+{
+    return h->ran_persistent || (h->path == kPathPhase && h->tuning.persistent);
+}
+
 void fill_obs(const lattice *h, const int64_t *v, lat_obs *out)
 {
     out->sweep = h->done;
@@ -659,6 +713,23 @@ int enqueue_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
 {
     if (sweeps == 0) return LAT_OK;
     lattice *one[1] = {h};
+    if (h->path == kPathWords) {
+        // all the call's sweeps in one persistent launch where it can run
+        uint32_t *work = (uint32_t *)(h->d_scratch + kScrWork);
+        if (h->packed) {
+            const hipError_t e = launch_pack_int8((const int8_t *)h->d_state, work, h->L, stream);
+            if (e != hipSuccess) return hip_fail(e, "int8 pack launch");
+        }
+        bool ran = false;
+        int rc = enqueue_words_persistent(h, 1, sweeps, nullptr, stream, &ran);
+        if (rc == LAT_OK && !ran) rc = enqueue_offchip_sweeps(one, 1, nullptr, sweeps, stream, /*convert=*/false);
+        if (rc) return rc;
+        if (h->packed) {
+            const hipError_t e = launch_unpack_int8(work, (int8_t *)h->d_state, h->L, stream);
+            if (e != hipSuccess) return hip_fail(e, "int8 unpack launch");
+        }
+        return LAT_OK;
+    }
     if (h->path != kPathLds) return enqueue_offchip_sweeps(one, 1, nullptr, sweeps, stream);
     // a lone lattice is not autotuned (tuning synchronises); it takes the
     // block size tuned for its shape by an earlier batch, else the default
@@ -855,7 +926,7 @@ int lattice_observables_batch(lattice *const *hs, int32_t count, void *d_out, si
         // lattices swept by the persistent kernel: its bounded device-wide
         // barrier flags a time-out in the lattice's error word
         for (int32_t i = 0; i < count && e == hipSuccess; ++i) {
-            if (hs[i]->path != kPathPhase || !hs[i]->tuning.persistent) continue;
+            if (!barrier_may_time_out(hs[i])) continue;
             uint32_t err = 0;
             e = hipMemcpy(&err, hs[i]->d_scratch + kScrErr, sizeof(err), hipMemcpyDeviceToHost);
             if (e == hipSuccess && (err & 1u))
@@ -883,7 +954,11 @@ int lattice_sweep_series(lattice *h, uint32_t intervals, uint32_t every, void *d
             const hipError_t e = launch_pack_int8((const int8_t *)h->d_state, work, h->L, st);
             if (e != hipSuccess) return hip_fail(e, "int8 pack launch");
         }
-        for (uint32_t k = 0; k < intervals; ++k) {
+        // the whole series in persistent launches where they can run
+        bool ran = false;
+        const int rc0 = enqueue_words_persistent(h, intervals, every, (long long *)d_series, st, &ran);
+        if (rc0) return rc0;
+        for (uint32_t k = 0; k < intervals && !ran; ++k) {
             const int rc = h->path == kPathLds ? enqueue_lds_sweeps(one, 1, nullptr, every, st, /*tune=*/false)
                                                : enqueue_offchip_sweeps(one, 1, nullptr, every, st, /*convert=*/false);
             if (rc) return rc;

@@ -71,7 +71,7 @@ extern "C" int lattice_observables_batch_noalloc(lattice *const *hs, int32_t cou
         // lattices swept by the persistent kernel: its bounded device-wide
         // barrier flags a time-out in the lattice's error word
         for (int32_t i = 0; i < count; ++i) {
-            if (hs[i]->path != kPathPhase || !hs[i]->tuning.persistent) continue;
+            if (!barrier_may_time_out(hs[i])) continue;
             uint32_t err = 0;
             const hipError_t e = hipMemcpy(&err, hs[i]->d_scratch + lat::kScrErr, sizeof(err), hipMemcpyDeviceToHost);
             if (e != hipSuccess) return hip_fail(e, "lattice_observables_batch_noalloc");

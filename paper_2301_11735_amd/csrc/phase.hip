@@ -284,32 +284,6 @@ __global__ void __launch_bounds__(1024, MinWaves) k_phase_2bit(PhaseArgs a, int 
     block_reduce_add<3>(tr, a.track + 3 * (size_t)blockIdx.x);
 }
 
-// Device-wide barrier between phases of the persistent kernel: every block
-// arrives once per phase on a monotonic counter.  Release: the fence writes
-// this block's results back past the compute unit's caches before the
-// arrival; acquire: the fence after the wait invalidates them.  The wait is
-// bounded: after about 2^24 polls the block raises the error flag and goes
-// on (results are then invalid and reported as an error), so no wave can
-// spin forever.
-__device__ __forceinline__ void grid_barrier(unsigned *counter, unsigned target, unsigned *err)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        atomicAdd(counter, 1u);
-        unsigned polls = 0;
-        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++polls > (1u << 24)) {
-                atomicOr(err, 1u);
-                break;
-            }
-        }
-        __threadfence();
-    }
-    __syncthreads();
-}
-
 // Persistent form: `sweeps` sweeps from sweep a.s_lo|a.s_hi in one launch of
 // co-resident blocks (cooperative launch), tables staged once, schedules
 // computed on the device, a device-wide barrier after every phase.

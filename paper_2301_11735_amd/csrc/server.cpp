@@ -1,18 +1,28 @@
-// Serving loop over the batched kernel: simulation requests arrive at any
+// Serving loop over the batched kernels: simulation requests arrive at any
 // time, are admitted into a caller-owned device pool when memory and a slot
-// are free, advance together (one batched launch per step, continuous
-// batching: new requests join between steps), and are harvested when done.
+// are free, advance together (continuous batching: new requests join between
+// steps), and are harvested when done.
 //
-// Each step gives every resident lattice about the same time on its compute
-// unit: a sweep of N sites costs about (N + kSweepCostSites) site-update
-// times (a fixed part -- four phase barriers and the latency of a phase's
-// dependent LDS reads -- plus a part proportional to N; on MI355X the fixed
-// part is worth about 11,000 site updates), so a lattice gets
+// A step advances the resident lattices on two streams at once.  Lattices on
+// the on-chip path (L <= 256 by default) share one batched launch, one block
+// per lattice, on the server's stream.  Each gets about the same time on its
+// compute unit: a sweep of N sites costs about (N + kSweepCostSites)
+// site-update times (a fixed part -- four phase barriers and the latency of
+// a phase's dependent LDS reads -- plus a part proportional to N; on MI355X
+// the fixed part is worth about 11,000 site updates), so a lattice gets
 // max(1, quantum / (N + kSweepCostSites)) sweeps, capped by what the request
 // still needs.  Blocks then end together, so a step is not held up by small
-// lattices doing many cheap sweeps and large requests advance at their full
-// rate.  Results are bit-identical to running the same request alone: a
-// lattice's chain depends only on its parameters, seed and sweep index.
+// lattices doing many cheap sweeps.  The larger lattices (L = 512) take the
+// multi-block word kernel, spread over many compute units, on a second
+// stream that keeps its own pace: while fewer than kSideChunks of its chunks
+// are in flight, a step queues the next one, max(1, quantum /
+// kWordsSweepCostSites) sweeps of every such lattice in one launch per phase
+// (a sweep costs about kWordsSweepCostSites site-update times of the on-chip
+// kernel whatever their number, as the launches are latency-bound), and a
+// finished lattice is harvested once the chunk holding its last sweep has
+// completed.  Results are bit-identical to running the same
+// request alone: a lattice's chain depends only on its parameters, seed and
+// sweep index.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,6 +45,13 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr uint64_t kSweepCostSites = 11000;
+// A multi-block sweep of a lattice of L = 512 takes about 22 us on MI355X
+// (four dependent phase launches), the time the on-chip kernel needs for
+// about 100,000 site updates on its compute unit.
+constexpr uint64_t kWordsSweepCostSites = 100000;
+// Chunks of the second stream in flight at once: the next one is queued
+// while the previous runs, so that stream never waits for the host.
+constexpr int kSideChunks = 2;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -100,6 +117,7 @@ struct Request {
     size_t off = 0, bytes = 0;
     lattice *h = nullptr;
     lat_obs obs{};
+    uint64_t last_chunk = 0;  // second-stream chunk holding its last sweep (multi-block lattices)
     std::vector<int8_t> final_codes;
     bool keep_state = false;
     double t_submit = 0, t_admit = 0, t_finish = 0;
@@ -114,6 +132,9 @@ struct lat_server {
     int32_t max_slots = 0;
     uint64_t quantum = 0;
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;               // multi-block lattices advance here, beside the on-chip launch
+    hipEvent_t chunk_done[kSideChunks] = {};  // recorded after chunk c in slot c % kSideChunks
+    uint64_t chunks_queued = 0, chunks_done = 0;
     std::unique_ptr<PoolAllocator> alloc;
     std::deque<uint64_t> queue;
     std::vector<uint64_t> resident;
@@ -225,27 +246,70 @@ int lat_server_step(lat_server *s, int32_t *n_finished)
         if (n_finished) *n_finished = 0;
         if (s->resident.empty()) return LAT_OK;
 
-        std::vector<lattice *> hs;
-        std::vector<uint32_t> sw;
+        bool any_big = false;
+        for (uint64_t id : s->resident) any_big = any_big || s->reqs[id]->h->path != kPathLds;
+        if (any_big && !s->side) {
+            // the second stream and its events, made when first needed
+            hipError_t e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
+            for (int i = 0; i < kSideChunks && e == hipSuccess; ++i)
+                e = hipEventCreateWithFlags(&s->chunk_done[i], hipEventDisableTiming);
+            if (e != hipSuccess) return hip_fail(e, "lat_server_step: second stream");
+        }
+        // chunks of the second stream seen complete
+        while (s->chunks_done < s->chunks_queued) {
+            const hipError_t q = hipEventQuery(s->chunk_done[s->chunks_done % kSideChunks]);
+            if (q == hipErrorNotReady) break;
+            if (q != hipSuccess) return hip_fail(q, "lat_server_step: second stream");
+            ++s->chunks_done;
+        }
+        const bool side_room = s->chunks_queued - s->chunks_done < (uint64_t)kSideChunks;
+
+        std::vector<lattice *> hs, big;
+        std::vector<uint32_t> sw, big_sw;
+        std::vector<Request *> big_reqs;
         for (uint64_t id : s->resident) {
             Request &r = *s->reqs[id];
+            if (r.done >= r.sweeps) continue;  // all its sweeps are enqueued
+            const bool on_chip = r.h->path == kPathLds;
+            if (!on_chip && !side_room) continue;
             const uint64_t N = (uint64_t)r.params.L * r.params.L;
-            const uint32_t want = (uint32_t)std::max<uint64_t>(1, s->quantum / (N + kSweepCostSites));
+            const uint64_t cost = on_chip ? N + kSweepCostSites : kWordsSweepCostSites;
+            const uint32_t want = (uint32_t)std::max<uint64_t>(1, s->quantum / cost);
             const uint32_t k = std::min(want, r.sweeps - r.done);
-            hs.push_back(r.h);
-            sw.push_back(k);
+            (on_chip ? hs : big).push_back(r.h);
+            (on_chip ? sw : big_sw).push_back(k);
+            if (!on_chip) big_reqs.push_back(&r);
             r.done += k;
             s->site_updates += N * k;
         }
-        rc = enqueue_lds_sweeps(hs.data(), (int32_t)hs.size(), sw.data(), 0, s->stream);
-        if (rc) return rc;
-        ++s->steps;
+        if (!big.empty()) {
+            // a new chunk on the second stream: nothing to wait for, since a
+            // lattice's set-up synchronised before it became resident
+            rc = enqueue_offchip_sweeps(big.data(), (int32_t)big.size(), big_sw.data(), 0, s->side);
+            if (rc) return rc;
+            const hipError_t e = hipEventRecord(s->chunk_done[s->chunks_queued % kSideChunks], s->side);
+            if (e != hipSuccess) return hip_fail(e, "lat_server_step");
+            for (Request *r : big_reqs)
+                if (r->done >= r->sweeps) r->last_chunk = s->chunks_queued;
+            ++s->chunks_queued;
+        }
+        if (!hs.empty()) {
+            rc = enqueue_lds_sweeps(hs.data(), (int32_t)hs.size(), sw.data(), 0, s->stream);
+            if (rc) return rc;
+        }
+        if (!hs.empty() || !big.empty()) ++s->steps;
 
+        // Harvest: on-chip lattices with all their sweeps enqueued (their
+        // work is ordered before the harvest on the server's stream), and
+        // multi-block ones once the chunk holding their last sweep has
+        // completed on the second stream.
         std::vector<lattice *> fin;
         std::vector<uint64_t> fin_ids, keep;
         for (uint64_t id : s->resident) {
             Request &r = *s->reqs[id];
-            if (r.done >= r.sweeps) {
+            const bool ready =
+                r.done >= r.sweeps && (r.h->path == kPathLds || (r.last_chunk < s->chunks_done));
+            if (ready) {
                 fin.push_back(r.h);
                 fin_ids.push_back(id);
             } else {
@@ -334,10 +398,15 @@ int lat_server_destroy(lat_server *s)
 {
     return guarded("lat_server_destroy", [&]() -> int {
         if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
-        hipError_t e = hipStreamSynchronize(s->stream);
+        hipError_t e = s->side ? hipStreamSynchronize(s->side) : hipSuccess;
+        const hipError_t e2 = hipStreamSynchronize(s->stream);
+        if (e == hipSuccess) e = e2;
         for (auto &kv : s->reqs)
             if (kv.second->h) lattice_destroy(kv.second->h);
         s->alloc.reset();
+        for (hipEvent_t ev : s->chunk_done)
+            if (ev) (void)hipEventDestroy(ev);
+        if (s->side) (void)hipStreamDestroy(s->side);
         delete s;
         return e == hipSuccess ? LAT_OK : hip_fail(e, "lat_server_destroy");
     });

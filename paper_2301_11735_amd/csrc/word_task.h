@@ -32,6 +32,129 @@ struct WordPhase {
     uint32_t s_lo, s_hi, key0, key1;
 };
 
+// Lattice word accessors.  Coh = false: ordinary loads and stores (the
+// lattice in LDS, or in global memory within one launch, whose end makes the
+// writes visible).  Coh = true: loads and stores at device coherence, which
+// no compute unit's or die's cache keeps stale, for the persistent kernels
+// whose blocks exchange lattice words across device-wide barriers without
+// cache write-back or invalidation.  Read-modify-writes are device-scope
+// atomics in both cases.
+template <bool Coh>
+__device__ __forceinline__ uint32_t ldw(const uint32_t *p, uint32_t i)
+{
+    if constexpr (Coh)
+        return __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        return p[i];
+}
+template <bool Coh>
+__device__ __forceinline__ void stw(uint32_t *p, uint32_t i, uint32_t v)
+{
+    if constexpr (Coh)
+        __hip_atomic_store(p + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        p[i] = v;
+}
+// 16 sites of the class row at word offset `row`, starting at class position
+// xs (periodic), as load16 but through ldw.
+template <bool Coh>
+__device__ __forceinline__ uint32_t ld16(const uint32_t *st, uint32_t row, int W, int xs)
+{
+    const int jw = xs >> 4, sh = xs & 15;
+    const uint32_t w0 = ldw<Coh>(st, row + (uint32_t)jw);
+    const uint32_t w1 = ldw<Coh>(st, row + (uint32_t)(jw + 1 == W ? 0 : jw + 1));
+    return sh ? __builtin_amdgcn_alignbit(w1, w0, 2u * (uint32_t)sh) : w0;
+}
+
+// Device-wide barrier for kernels whose lattice words are all accessed at
+// device coherence (ldw/stw<true> and device-scope atomics): every wave
+// waits for its own memory operations to complete, the block meets, one
+// thread arrives on the monotonic counter and waits for the others; no
+// cache write-back or invalidation is needed.  The wait is bounded as in
+// grid_barrier (time-out flag, then go on).
+__device__ __forceinline__ void grid_barrier_coherent(unsigned *counter, unsigned target, unsigned *err)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned polls = 0;
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++polls > (1u << 24)) {
+                atomicOr(err, 1u);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// The fields of WordPhase for phase p of a sweep with schedule (r, m, k), on
+// a lattice of side L with key (key0, key1); s is the sweep index.
+__device__ __forceinline__ void word_phase_setup(WordPhase &f, int L, uint32_t key0, uint32_t key1, uint64_t s,
+                                                 int p, int r, const int (&mm)[4], const int (&kk)[4])
+{
+    f.W = L >> 6;
+    f.H = L >> 1;
+    f.Lq = L >> 2;
+    f.magicW = f.W == 1 ? 0u : (uint32_t)((0x100000000ull + (uint64_t)f.W - 1u) / (uint64_t)f.W);
+    f.key0 = key0;
+    f.key1 = key1;
+    f.s_lo = (uint32_t)s;
+    f.s_hi = (uint32_t)(s >> 32);
+    const uint32_t csz = (uint32_t)f.H * (uint32_t)f.W;
+    f.k = kk[p];
+    f.p = p;
+    f.pb = (p + r) & 3;
+    const int carry = (p + r) >> 2;
+    f.dX = mm[p] + carry >= f.Lq ? mm[p] + carry - f.Lq : mm[p] + carry;
+    f.oA0 = (uint32_t)p * csz;
+    f.oAL = (uint32_t)(p > 0 ? p - 1 : 3) * csz;
+    f.oAR = (uint32_t)(p < 3 ? p + 1 : 0) * csz;
+    f.oAV = (uint32_t)(4 + p) * csz;
+    f.oB0 = (uint32_t)(4 + f.pb) * csz;
+    f.oBL = (uint32_t)(f.pb > 0 ? 4 + f.pb - 1 : 7) * csz;
+    f.oBR = (uint32_t)(f.pb < 3 ? 4 + f.pb + 1 : 4) * csz;
+    f.oBV = (uint32_t)f.pb * csz;
+}
+
+// Observable sums of class word i (16 sites) of a lattice of side L in the
+// 2-bit class layout: sum S, sum S^2, the S S and sigma sigma bonds to the
+// right and lower neighbours, sum sigma, and the staggered sums.  The right
+// neighbours are the same word of the next class (or class 0 of the row,
+// one site on), the lower ones the same word of the paired row class.
+template <bool Coh = false>
+__device__ __forceinline__ void obs_word_2bit(const uint32_t *st, int L, uint32_t i, long long (&v)[7])
+{
+    const int W = L >> 6, H = L >> 1, Lq = L >> 2;
+    const uint32_t csz = (uint32_t)H * W;
+    const int c = (int)(i / csz);
+    const uint32_t rem = i - (uint32_t)c * csz;
+    const int Y = (int)(rem / W), j = (int)(rem - (uint32_t)Y * W);
+    const int cx = c & 3, cy = c >> 2;
+    const uint32_t w = ldw<Coh>(st, i);
+    const uint32_t wr = cx < 3 ? ldw<Coh>(st, i + csz)
+                               : ld16<Coh>(st, (uint32_t)(4 * cy) * csz + (uint32_t)Y * W, W,
+                                           16 * j + 1 == Lq ? 0 : 16 * j + 1);
+    const uint32_t wd = cy == 0 ? ldw<Coh>(st, i + 4 * csz)
+                                : ldw<Coh>(st, (uint32_t)cx * csz + (uint32_t)(Y + 1 == H ? 0 : Y + 1) * W + j);
+    const uint32_t h = (w >> 1) & kM5, l = w & kM5;
+    const int sumS = __popc(h & ~l) - __popc(h & l);
+    const int sumG = __popc((h | l) ^ kM5) - __popc(l & ~h);
+    int bSS = 0, bss = 0;
+    bond_sums(h, l, (wr >> 1) & kM5, wr & kM5, bSS, bss);
+    bond_sums(h, l, (wd >> 1) & kM5, wd & kM5, bSS, bss);
+    const int sg = ((cx + cy) & 1) ? -1 : 1;
+    v[0] += sumS;
+    v[1] += __popc(h);
+    v[2] += bSS;
+    v[3] += bss;
+    v[4] += sumG;
+    v[5] += sg * sumG;
+    v[6] += sg * sumS;
+}
+
 // Barrier = true keeps the compiler from interleaving the Philox calls of a
 // task (fewer live registers, needed at 1024 threads per block); without it
 // the calls overlap each other's LDS table lookups.
@@ -78,7 +201,8 @@ __device__ __forceinline__ uint32_t task_call0(const WordPhase &f, uint32_t task
 // lane stores the a-word, which no other word reads or writes in the phase,
 // and applies the two b-word changes as atomics; one store and two atomics
 // per word instead of 3Q atomics.  Every lane of a word must be active.
-template <int Q, bool Barrier, bool Pipe = false, bool Combine = false>
+// Coh: the lattice words are read and written through ldw/stw<true>.
+template <int Q, bool Barrier, bool Pipe = false, bool Combine = false, bool Coh = false>
 __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uint32_t task, const uint2 *s_tab,
                                           const uint4 *s_transd, int (&tr)[3], u32x4 *pre = nullptr,
                                           uint64_t ns = 0, int np = 0)
@@ -99,14 +223,14 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
     const uint32_t roU = (uint32_t)(Y == 0 ? H - 1 : Y - 1) * W;
     const uint32_t robD = (uint32_t)(Yb + 1 == H ? 0 : Yb + 1) * W;
 
-    const uint32_t A0 = lat[f.oA0 + ro + j];
-    const uint32_t B0 = load16(lat, f.oB0 + rob, W, Xb);
+    const uint32_t A0 = ldw<Coh>(lat, f.oA0 + ro + j);
+    const uint32_t B0 = ld16<Coh>(lat, f.oB0 + rob, W, Xb);
     SideSums sa, sb;
     if constexpr (Q == 1) {
-        sa = side_sums(load16(lat, f.oAL + ro, W, xAL), load16(lat, f.oAR + ro, W, xAR), lat[f.oAV + roU + j],
-                       lat[f.oAV + ro + j]);
-        sb = side_sums(load16(lat, f.oBL + rob, W, xBL), load16(lat, f.oBR + rob, W, xBR),
-                       load16(lat, f.oBV + rob, W, Xb), load16(lat, f.oBV + robD, W, Xb));
+        sa = side_sums(ld16<Coh>(lat, f.oAL + ro, W, xAL), ld16<Coh>(lat, f.oAR + ro, W, xAR),
+                       ldw<Coh>(lat, f.oAV + roU + j), ldw<Coh>(lat, f.oAV + ro + j));
+        sb = side_sums(ld16<Coh>(lat, f.oBL + rob, W, xBL), ld16<Coh>(lat, f.oBR + rob, W, xBR),
+                       ld16<Coh>(lat, f.oBV + rob, W, Xb), ld16<Coh>(lat, f.oBV + robD, W, Xb));
     } else {
         // The Q threads of a word are Q consecutive lanes.  Lanes of the
         // first half sum a-side neighbour words, the others b-side ones,
@@ -123,7 +247,7 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
             const int kk = k0 + i;
             const uint32_t b = kk == 0 ? base[0] : kk == 1 ? base[1] : kk == 2 ? base[2] : base[3];
             const int x = kk == 0 ? xs[0] : kk == 1 ? xs[1] : kk == 2 ? xs[2] : xs[3];
-            side_add(part, load16(lat, b, W, x));
+            side_add(part, ld16<Coh>(lat, b, W, x));
         }
         SideSums full = part, other;
         if constexpr (Q >= 4) {
@@ -231,7 +355,7 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
             cB |= lane_xor<4>(cB);
         }
         if (q == 0) {
-            lat[f.oA0 + ro + j] = A0 ^ cA;
+            stw<Coh>(lat, f.oA0 + ro + j, A0 ^ cA);
             atomicXor(&lat[f.oB0 + rob + (uint32_t)jb], cB << (2 * shb));
             const uint32_t hi = shb ? cB >> (32 - 2 * shb) : 0u;
             atomicXor(&lat[f.oB0 + rob + (uint32_t)(jb + 1 == W ? 0 : jb + 1)], hi);

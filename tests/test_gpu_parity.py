@@ -200,11 +200,15 @@ def test_phase_kernel_path_matches_oracle(spec, monkeypatch):
     SMALL.with_(L=1024, encoding=1, n=0.3, T=0.4, seed=76),
     SMALL.with_(L=2048, encoding=1, T=1.7, seed=77),
 ], ids=lambda s: f"enc{s.encoding}-L{s.L}")
-def test_word_path_matches_oracle(spec, monkeypatch):
+@pytest.mark.parametrize("persistent", ["1", "0"], ids=["persistent", "per-phase"])
+def test_word_path_matches_oracle(spec, persistent, monkeypatch):
     """The multi-block word kernel (Q lanes per a-word, schedules computed on
     the device, several blocks per lattice) at every size it takes, both
-    encodings: the same chain as the oracle, bit for bit."""
+    encodings, as one persistent launch per call (device-wide barriers
+    between phases) and as one launch per phase: the same chain as the
+    oracle, bit for bit."""
     monkeypatch.setenv("LATTICE_PATH", "words")
+    monkeypatch.setenv("LATTICE_WORDS_PERSISTENT", persistent)
     _run_parity(spec, [1, 3, 10] if spec.L <= 1024 else [1, 2])
 
 
@@ -358,6 +362,46 @@ def test_served_results_equal_alone_and_oracle():
         assert [ob["track_nD"], ob["track_nV"], ob["track_nJ"]] == o.track.tolist()
 
 
+def test_served_config_sizes_equal_alone_and_oracle():
+    """The served configuration's sizes and sweep counts: L in {64, 128, 256,
+    512}, 500-800 sweeps, the full parameter ranges.  The L = 512 requests
+    advance on the multi-block word kernel on the server's second stream
+    while the others share the on-chip launch; every request's result equals
+    the same request run alone, and two of L = 512 and two of L = 256 equal
+    the oracle."""
+    _say("case serving, served sizes")
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_2301_11735_amd import serve as serve_mod
+
+    reqs = workloads.request_stream(rate_per_s=40.0, duration_s=1.0, seed=12, sweep_range=(500, 800))
+    assert len(reqs) > 20 and {r.spec.L for r in reqs} == {64, 128, 256, 512}
+    done, wall, st = serve_mod.serve(reqs, 8 << 20, slots=32, quantum=1 << 22, keep_state=True, progress=False)
+    assert len(done) == len(reqs)
+    for r in reqs:
+        s = r.spec
+        g = lat.Lattice(s.L, s.n, s.Delta, s.V, s.J, s.T, s.seed, encoding=s.encoding)
+        g.sweep(s.sweeps)
+        assert np.array_equal(g.read_state(), done[r.index]["codes"]), r.index
+        assert g.observables().as_dict() == done[r.index]["obs"], r.index
+        g.destroy()
+    picks = [r for r in reqs if r.spec.L == 512][:2] + [r for r in reqs if r.spec.L == 256][:2]
+
+    def run_oracle(r):
+        o = _oracle(r.spec)
+        o.sweeps(r.spec.sweeps)
+        return o
+
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        oracles = list(ex.map(run_oracle, picks))
+    for r, o in zip(picks, oracles):
+        assert np.array_equal(o.codes, done[r.index]["codes"]), r.index
+        ob = done[r.index]["obs"]
+        assert [ob["sum_S"], ob["n_charged"], ob["bond_SS"], ob["bond_ss"], ob["M"], ob["M_stag"],
+                ob["C_stag"]] == o.observables().tolist()
+        assert [ob["track_nD"], ob["track_nV"], ob["track_nJ"]] == o.track.tolist()
+
+
 @pytest.mark.parametrize("spec", [
     SMALL.with_(L=576, encoding=1, seed=81),                     # 9 words per class row
     SMALL.with_(L=1024, encoding=1, T=0.6, n=-0.15, seed=82),
@@ -488,17 +532,39 @@ def test_batch_graph_replays_match_eager_and_oracle(kind, threads, monkeypatch):
         assert np.array_equal(g.read_state(), o.codes)
 
 
+def test_mid_series_per_phase_launches_match_oracle(monkeypatch):
+    """The mid lattice's observation series through one launch per phase (the
+    persistent form switched off): the same records as the oracle."""
+    monkeypatch.setenv("LATTICE_WORDS_PERSISTENT", "0")
+    spec = workloads.MID
+    _say("case series per-phase L=1024")
+    g, o = _pair(spec)
+    recs = g.sweep_series(6, 1)
+    for k, r in enumerate(recs):
+        o.sweeps(1)
+        assert r.ints() == o.observables().tolist(), k
+        assert [r.track_nD, r.track_nV, r.track_nJ] == o.track.tolist(), k
+        assert r.sweep == k + 1
+    _assert_same(g, o, "after the series")
+    g.destroy()
+
+
 @pytest.mark.parametrize("spec,every,intervals", [
     (workloads.MID, 1, 12),                                        # int8 L=1024 on its 2-bit copy, every sweep
     (SMALL.with_(L=64, encoding=1, seed=91), 3, 8),                # on-chip path
     (SMALL.with_(L=4096, encoding=0, T=1.1, seed=92), 1, 3),       # phase kernel, packed int8
     (SMALL.with_(L=100, seed=93), 2, 5),                           # int8 with L % 64 != 0
-], ids=["mid", "lds", "phase-int8", "int8-L100"])
-def test_device_observation_series_matches_oracle(spec, every, intervals):
+    (SMALL.with_(L=576, encoding=1, seed=94), 3, 4),               # words path, 2-bit, 9 words per class row
+    (SMALL.with_(L=2048, encoding=1, T=0.7, seed=95), 1, 2),       # words path, Q = 2
+], ids=["mid", "lds", "phase-int8", "int8-L100", "words-L576", "words-L2048"])
+@pytest.mark.parametrize("persistent", ["1", "0"], ids=["persistent", "per-phase"])
+def test_device_observation_series_matches_oracle(spec, every, intervals, persistent, monkeypatch):
     """lattice_sweep_series keeps the observables of every interval on the
     device (no host synchronisation between intervals); each record equals the
     oracle's observables, tracker and sweep count after that interval, and
-    the state after the series is the oracle's."""
+    the state after the series is the oracle's.  Lattices on the multi-block
+    path run the series as persistent launches or as launches per phase."""
+    monkeypatch.setenv("LATTICE_WORDS_PERSISTENT", persistent)
     _say(f"case series L={spec.L} enc={spec.encoding} every={every} intervals={intervals}")
     g, o = _pair(spec)
     g.sweep(2)

@@ -72,16 +72,23 @@ def test_scan_ising_limit_4x4_matches_enumeration(T):
 
 def test_heat_capacity_curve_4x4_matches_exact():
     """C(T) of the 4x4 sector n = 1/8 across the range where the exact curve has
-    its structure; prints the table (T, C from 64 replicas, exact C)."""
+    its structure; prints the table (T, C from 64 replicas, exact C).  Below
+    T = 0.5 the chain leaves its low-energy states rarely, so those points get a
+    long burn-in and a long series; every point's error bar must stay under 30%
+    of C, so that agreement within it means something."""
     L, N, Q = 4, 16, 2
     Delta, V, J, n = 0.25, 0.5, 1.0, 0.125
-    temps = [0.25, 0.35, 0.5, 0.7, 1.0, 1.4, 2.0, 3.0]
     _say("case thermo 4x4 C(T) curve")
-    rows = thermo.scan(L, n, Delta, V, J, temps, replicas=64, sweeps=8000, burn=500, every=1, seed0=1100)
-    _say("T  C_gpu  C_err  C_exact  e_gpu  e_err  e_exact")
+    rows = thermo.scan(L, n, Delta, V, J, [0.25, 0.35], replicas=64, sweeps=160000, burn=20000, every=2, seed0=1000)
+    rows += thermo.scan(L, n, Delta, V, J, [0.5, 0.7, 1.0, 1.4, 2.0, 3.0], replicas=64, sweeps=8000, burn=500,
+                        every=1, seed0=1100)
+    _say("T  C_gpu  C_err  C_exact  z_C  e_gpu  e_err  e_exact  z_e")
     for row in rows:
         ex = exact.sector_averages(L, Q, Delta, V, J, row["T"])
+        e_ex = ex["E"] / N
         _say(f"{row['T']:.2f} {row['C']:.5f} {row['C_err']:.5f} {ex['C']:.5f} "
-             f"{row['e']:.5f} {row['e_err']:.5f} {ex['E'] / N:.5f}")
+             f"{(row['C'] - ex['C']) / row['C_err']:+.2f} {row['e']:.5f} {row['e_err']:.5f} {e_ex:.5f} "
+             f"{(row['e'] - e_ex) / row['e_err']:+.2f}")
+        assert row["C_err"] < 0.3 * ex["C"], f"T={row['T']}: error bar {row['C_err']:.4f} too wide for C={ex['C']:.4f}"
         _close("C", row["C"], row["C_err"], ex["C"], row["T"])
-        _close("e", row["e"], row["e_err"], ex["E"] / N, row["T"])
+        _close("e", row["e"], row["e_err"], e_ex, row["T"])
