@@ -117,7 +117,14 @@ int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void 
 /* Advance by `sweeps` sweeps (section 3.1 update, section 3.2 parallel form):
  * each sweep is four phases of N/8 non-interacting coupled pairs, so every
  * site is updated once per sweep.  Asynchronous on the handle's stream.
- * Errors: LAT_ESTATE, LAT_EHIP. */
+ * Lattices with L % 64 == 0 and 256 < L <= 512 advance in one cooperative
+ * launch per call, whose blocks must all be resident at once, with a
+ * device-wide barrier after every phase: kernels of other streams running
+ * at the same time can delay it, and a barrier that waits longer than about
+ * 0.2 s marks the state invalid, which the next read (lattice_observables,
+ * lattice_observables_batch, lattice_series_read) reports as LAT_EHIP.
+ * LATTICE_WORDS_PERSISTENT=0 in the environment at the call selects one
+ * launch per phase instead.  Errors: LAT_ESTATE, LAT_EHIP. */
 int lattice_sweep(lattice *h, uint32_t sweeps);
 
 /* Reduce the current configuration to its integer observables, read the

@@ -231,19 +231,21 @@ __device__ __forceinline__ void device_schedule(int L, uint32_t k0, uint32_t k1,
 // (a wave's fence waits only for its own stores and atomics), so the block's
 // results are past the compute unit's caches before its arrival; acquire:
 // the fence after the wait invalidates the caches the block reads through.
-// The wait is bounded: after about 2^24 polls the block raises the error
-// flag and goes on (results are then invalid and reported as an error), so
-// no wave can spin forever.
+// The wait is bounded in time (kBarrierTimeoutTicks of the device's
+// constant-rate wall clock, 0.2 s at its 100 MHz): then the block raises the
+// error flag and goes on (results are then invalid and reported as an
+// error), so no wave can spin for long.
+constexpr long long kBarrierTimeoutTicks = 20000000;
 __device__ __forceinline__ void grid_barrier(unsigned *counter, unsigned target, unsigned *err)
 {
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
         atomicAdd(counter, 1u);
-        unsigned polls = 0;
+        const long long t0 = wall_clock64();
         while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
-            if (++polls > (1u << 24)) {
+            if (wall_clock64() - t0 > kBarrierTimeoutTicks) {
                 atomicOr(err, 1u);
                 break;
             }

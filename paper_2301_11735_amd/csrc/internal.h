@@ -33,10 +33,8 @@ struct lattice {
     lat::Tuning2Bit tuning{0, 0, 0, 0};
     int path = kPathLds;
     bool packed = false;  // int8 swept on the 2-bit copy at scratch + kScrWork
-    // persistent multi-block launches (kPathWords): blocks per launch, 0 when
-    // unavailable, -1 before the first look-up; set once one has run, so that
-    // reads check the barrier's time-out flag
-    int series_grid = -1;
+    // set once a persistent launch has swept it, so that reads check the
+    // device-wide barrier's time-out flag
     bool ran_persistent = false;
     uint32_t magic = 0;
 };
@@ -81,17 +79,23 @@ int enqueue_observables_batch(lattice *const *hs, int32_t count, unsigned long l
 // Lattices on the off-chip paths (words, phase): lattice i by sweeps[i]
 // (null: `uniform`); int8 ones are packed before and unpacked after.
 // convert = false: packed lattices are already on (and stay on) their copy.
+// persistent = false: the multi-block lattices take one launch per phase,
+// never the cooperative persistent launch, whose blocks must all be resident
+// at once (callers whose other streams run kernels at the same time, like
+// the server, would otherwise leave it waiting for compute units).
 int enqueue_offchip_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps, uint32_t uniform,
-                           hipStream_t stream, bool convert = true);
-// Sweeps (and, with records, an observation series: intervals x every sweeps,
-// a kSeriesRecord record after each interval) of one lattice on the
-// multi-block path as persistent launches.  *ran = false (nothing enqueued)
-// when the persistent form is off (by default above L = 512;
-// LATTICE_WORDS_PERSISTENT=0|1 overrides) or cannot be launched here; the
-// caller then uses the per-phase launches.  The lattice
-// must already be on its 2-bit copy if it is a packed int8 lattice.
-int enqueue_words_persistent(lattice *h, uint32_t intervals, uint32_t every, long long *records, hipStream_t stream,
-                             bool *ran);
+                           hipStream_t stream, bool convert = true, bool persistent = true);
+// Lattices of the multi-block path as persistent launches: lattice i by
+// sweeps[i] (null: `every`) with intervals = 1 and no records, or, with
+// records, an observation series of one lattice: intervals x every sweeps, a
+// kSeriesRecord record after each interval.  *ran = false (nothing
+// enqueued) when the persistent form is off (by default above L = 512, or
+// above L = 1024 for a series; LATTICE_WORDS_PERSISTENT=0|1 overrides) or
+// cannot be launched here; the
+// caller then uses the per-phase launches.  Packed int8 lattices must
+// already be on their 2-bit copy.
+int enqueue_words_persistent(lattice *const *hs, int32_t count, const uint32_t *sweeps, uint32_t intervals,
+                             uint32_t every, long long *records, hipStream_t stream, bool *ran);
 // Checks of lat_params (geometry, finite couplings, T > 0, the charge target
 // of eq. 2); writes the target charge and the charged count.
 int validate_params(const lat_params *p, int64_t *Q, int64_t *Nc);

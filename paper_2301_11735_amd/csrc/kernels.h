@@ -138,20 +138,27 @@ inline uint32_t words_blocks(int L, int Q)
 hipError_t launch_phase_words(const WordsArgs &a, int Q, hipStream_t s);
 // desc->next_sweep += sweeps[i] for every lattice of the series.
 hipError_t launch_advance_words(const WordsArgs &a, hipStream_t s);
-// Persistent multi-block form for one lattice: intervals x every sweeps in
-// one cooperative launch (device-wide barrier after every phase); with
-// records (kSeriesRecord bytes each, as launch_observables writes them), the
-// observables and tracker after every interval.  The lattice's barrier
-// counter is cleared and the records initialised by kernels enqueued first.
+// Persistent multi-block form: up to kWordsBatch lattices (blocks
+// first_block[i] .. first_block[i+1]-1 update lattice i) for intervals x
+// every sweeps in one cooperative launch, a device-wide barrier after every
+// phase; lattice i runs its first sweeps[i] of them.  With records (one
+// lattice, kSeriesRecord bytes each, as launch_observables writes them) the
+// observables and tracker after every interval.  The barrier counter (in
+// the first lattice's scratch) is cleared and the records initialised by
+// kernels enqueued first.
 struct WordsSeriesArgs {
-    uint8_t *scratch;
+    int count;
     uint32_t intervals, every;
     long long *records;  // null: no observables
+    uint8_t *scratch[kWordsBatch];
+    uint32_t sweeps[kWordsBatch];
+    uint32_t first_block[kWordsBatch + 1];
 };
-// Blocks of the persistent launch for side L, or 0 when co-residency cannot
-// be guaranteed (no cooperative launch); then the per-phase launches are used.
-int words_series_grid(int L, int Q);
-hipError_t launch_words_series(const WordsSeriesArgs &a, int Q, int grid, hipStream_t s);
+// Blocks of the persistent launch that can be resident at once (0 when
+// co-residency cannot be guaranteed: no cooperative launch); the caller then
+// uses the per-phase launches.
+int words_persistent_capacity(int Q);
+hipError_t launch_words_series(const WordsSeriesArgs &a, int Q, hipStream_t s);
 // int8 codes (row-major) <-> the 2-bit class layout, for L % 64 == 0.
 hipError_t launch_pack_int8(const int8_t *src, uint32_t *dst, int L, hipStream_t s);
 hipError_t launch_unpack_int8(const uint32_t *src, int8_t *dst, int L, hipStream_t s);

@@ -422,57 +422,121 @@ int enqueue_words_sweeps(lattice *const *hs, int32_t count, const uint32_t *swee
 
 }  // namespace
 
-constexpr int kWordsPersistentMaxL = 512;
+constexpr int kWordsPersistentMaxL = 512, kWordsPersistentSeriesMaxL = 1024;
 
-int enqueue_words_persistent(lattice *h, uint32_t intervals, uint32_t every, long long *records, hipStream_t stream,
-                             bool *ran)
+namespace {
+
+// Resident-block capacity of the persistent word kernel per (device, Q),
+// looked up once.
+int words_capacity(int Q)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({dev, Q});
+    if (it == cache.end()) it = cache.emplace(std::make_pair(dev, Q), words_persistent_capacity(Q)).first;
+    return it->second;
+}
+
+}  // namespace
+
+int enqueue_words_persistent(lattice *const *hs, int32_t count, const uint32_t *sweeps, uint32_t intervals,
+                             uint32_t every, long long *records, hipStream_t stream, bool *ran)
 {
     *ran = false;
-    if (h->path != kPathWords || intervals == 0 || every == 0) return LAT_OK;
-    // default: on up to L = 512, where it measured faster than one launch per
-    // phase (13.6 against 21.9 us a sweep at L = 512); above, its
-    // device-coherent loads, which bypass the L2, cost more than the launches
-    // they save (27 against 24 us at L = 1024).  LATTICE_WORDS_PERSISTENT=0|1
-    // overrides.
+    if (count <= 0 || intervals == 0 || every == 0) return LAT_OK;
+    int max_L = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        if (hs[i]->path != kPathWords) return LAT_OK;
+        max_L = std::max(max_L, hs[i]->L);
+    }
+    // default: on up to L = 512 for plain sweeps, where it measured faster
+    // than one launch per phase (13.6 against 21.9 us a sweep at L = 512);
+    // above, its device-coherent loads, which bypass the L2, cost more than
+    // the launches they save (27 against 24 us at L = 1024).  A series with
+    // its reductions every sweep measured 36.7 against 38.4 us a sweep at
+    // L = 1024 and needs one launch instead of seven per sweep, so series take
+    // it up to L = 1024.  LATTICE_WORDS_PERSISTENT=0|1 overrides.
     const char *v = std::getenv("LATTICE_WORDS_PERSISTENT");
-    if (v ? std::atoi(v) == 0 : h->L > kWordsPersistentMaxL) return LAT_OK;
-    const int Q = words_lanes(h->L);
-    if (h->series_grid < 0) h->series_grid = words_series_grid(h->L, Q);
-    if (h->series_grid <= 0) return LAT_OK;
+    if (v ? std::atoi(v) == 0 : max_L > (records ? kWordsPersistentSeriesMaxL : kWordsPersistentMaxL)) return LAT_OK;
+    if (records && count != 1) return fail(LAT_EINVAL, "an observation series holds one lattice");
+    const int Q = words_lanes(max_L);
+    const int capacity = words_capacity(Q);
+    if (capacity <= 0) return LAT_OK;
     // the barrier counter counts blocks x barriers: at most 2^20 barriers per
-    // launch keeps it far below 2^32
+    // launch keeps it below 2^32 for any resident grid
     constexpr uint64_t kMaxBarriers = 1u << 20;
     const uint64_t per_interval = 4ull * every + (records ? 1u : 0u);
-    if (per_interval > kMaxBarriers) {
-        if (records) return LAT_OK;  // such long intervals take the per-phase launches
-        // plain sweeps: split into launches of at most 2^18 sweeps
-        uint32_t left = every;
-        while (left > 0) {
-            const uint32_t n = std::min<uint32_t>(left, kMaxBarriers / 4);
-            const int rc = enqueue_words_persistent(h, 1, n, nullptr, stream, ran);
-            if (rc || !*ran) return rc;
-            left -= n;
+    if (per_interval > kMaxBarriers && records) return LAT_OK;  // such intervals take the per-phase launches
+    const uint32_t sweeps_cap = (uint32_t)(kMaxBarriers / 4);
+    const uint32_t intervals_cap = records ? (uint32_t)std::max<uint64_t>(1, kMaxBarriers / per_interval) : 1u;
+
+    // lattices in launches of at most kWordsBatch, each with its share of the
+    // resident blocks
+    for (int32_t g0 = 0; g0 < count; g0 += kWordsBatch) {
+        const int32_t n = std::min<int32_t>(kWordsBatch, count - g0);
+        const uint32_t share = std::max<uint32_t>(1, (uint32_t)capacity / (uint32_t)n);
+        uint32_t nb[kWordsBatch];
+        uint32_t total = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            nb[i] = std::min<uint32_t>({words_blocks(hs[g0 + i]->L, Q), share, (uint32_t)kMaxSlots});
+            total += nb[i];
         }
-        return LAT_OK;
+        if (total > (uint32_t)capacity) return *ran ? fail(LAT_EHIP, "persistent word launch does not fit") : LAT_OK;
+        if (records) {
+            lattice *h = hs[g0];
+            for (uint32_t k = 0; k < intervals; k += intervals_cap) {
+                WordsSeriesArgs a{};
+                a.count = 1;
+                a.intervals = std::min(intervals_cap, intervals - k);
+                a.every = every;
+                a.records = records + (kSeriesRecord / 8) * (size_t)k;
+                a.scratch[0] = h->d_scratch;
+                a.sweeps[0] = a.intervals * every;
+                a.first_block[0] = 0;
+                a.first_block[1] = nb[0];
+                const hipError_t e = launch_words_series(a, Q, stream);
+                if (e != hipSuccess) return hip_fail(e, "persistent word kernel launch");
+                h->done += (uint64_t)a.sweeps[0];
+            }
+            h->ran_persistent = true;
+            *ran = true;
+            continue;
+        }
+        uint32_t most = 0;
+        for (int32_t i = 0; i < n; ++i) most = std::max(most, sweeps ? sweeps[g0 + i] : every);
+        for (uint32_t c = 0; c < most; c += sweeps_cap) {
+            WordsSeriesArgs a{};
+            a.intervals = 1;
+            a.every = 0;
+            uint32_t blocks = 0;
+            for (int32_t i = 0; i < n; ++i) {
+                const uint32_t want = sweeps ? sweeps[g0 + i] : every;
+                const uint32_t k = want > c ? std::min(sweeps_cap, want - c) : 0u;
+                if (k == 0) continue;
+                a.scratch[a.count] = hs[g0 + i]->d_scratch;
+                a.sweeps[a.count] = k;
+                a.first_block[a.count] = blocks;
+                blocks += nb[i];
+                a.every = std::max(a.every, k);
+                ++a.count;
+                hs[g0 + i]->done += k;
+                hs[g0 + i]->ran_persistent = true;
+            }
+            a.first_block[a.count] = blocks;
+            if (a.count == 0) continue;
+            const hipError_t e = launch_words_series(a, Q, stream);
+            if (e != hipSuccess) return hip_fail(e, "persistent word kernel launch");
+        }
+        *ran = true;
     }
-    const uint32_t chunk = (uint32_t)std::min<uint64_t>(intervals, kMaxBarriers / per_interval);
-    for (uint32_t k = 0; k < intervals; k += chunk) {
-        WordsSeriesArgs a{};
-        a.scratch = h->d_scratch;
-        a.intervals = std::min(chunk, intervals - k);
-        a.every = every;
-        a.records = records ? records + (kSeriesRecord / 8) * (size_t)k : nullptr;
-        const hipError_t e = launch_words_series(a, Q, h->series_grid, stream);
-        if (e != hipSuccess) return hip_fail(e, "persistent word kernel launch");
-        h->done += (uint64_t)a.intervals * every;
-    }
-    h->ran_persistent = true;
-    *ran = true;
     return LAT_OK;
 }
 
 int enqueue_offchip_sweeps(lattice *const *hs, int32_t count, const uint32_t *sweeps, uint32_t uniform,
-                           hipStream_t stream, bool convert)
+                           hipStream_t stream, bool convert, bool persistent)
 {
     auto n_of = [&](int32_t i) { return sweeps ? sweeps[i] : uniform; };
     for (int32_t i = 0; i < count && convert; ++i) {
@@ -493,7 +557,12 @@ int enqueue_offchip_sweeps(lattice *const *hs, int32_t count, const uint32_t *sw
         }
     }
     if (!words.empty()) {
-        const int rc = enqueue_words_sweeps(words.data(), (int32_t)words.size(), words_n.data(), 0, stream);
+        bool ran = false;
+        int rc = persistent ? enqueue_words_persistent(words.data(), (int32_t)words.size(), words_n.data(), 1, 1,
+                                                       nullptr, stream, &ran)
+                            : LAT_OK;
+        if (rc == LAT_OK && !ran)
+            rc = enqueue_words_sweeps(words.data(), (int32_t)words.size(), words_n.data(), 0, stream);
         if (rc) return rc;
     }
     for (int32_t i = 0; i < count && convert; ++i) {
@@ -713,23 +782,7 @@ int enqueue_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
 {
     if (sweeps == 0) return LAT_OK;
     lattice *one[1] = {h};
-    if (h->path == kPathWords) {
-        // all the call's sweeps in one persistent launch where it can run
-        uint32_t *work = (uint32_t *)(h->d_scratch + kScrWork);
-        if (h->packed) {
-            const hipError_t e = launch_pack_int8((const int8_t *)h->d_state, work, h->L, stream);
-            if (e != hipSuccess) return hip_fail(e, "int8 pack launch");
-        }
-        bool ran = false;
-        int rc = enqueue_words_persistent(h, 1, sweeps, nullptr, stream, &ran);
-        if (rc == LAT_OK && !ran) rc = enqueue_offchip_sweeps(one, 1, nullptr, sweeps, stream, /*convert=*/false);
-        if (rc) return rc;
-        if (h->packed) {
-            const hipError_t e = launch_unpack_int8(work, (int8_t *)h->d_state, h->L, stream);
-            if (e != hipSuccess) return hip_fail(e, "int8 unpack launch");
-        }
-        return LAT_OK;
-    }
+    // the multi-block path takes the persistent launch where it can run
     if (h->path != kPathLds) return enqueue_offchip_sweeps(one, 1, nullptr, sweeps, stream);
     // a lone lattice is not autotuned (tuning synchronises); it takes the
     // block size tuned for its shape by an earlier batch, else the default
@@ -956,7 +1009,7 @@ int lattice_sweep_series(lattice *h, uint32_t intervals, uint32_t every, void *d
         }
         // the whole series in persistent launches where they can run
         bool ran = false;
-        const int rc0 = enqueue_words_persistent(h, intervals, every, (long long *)d_series, st, &ran);
+        const int rc0 = enqueue_words_persistent(one, 1, nullptr, intervals, every, (long long *)d_series, st, &ran);
         if (rc0) return rc0;
         for (uint32_t k = 0; k < intervals && !ran; ++k) {
             const int rc = h->path == kPathLds ? enqueue_lds_sweeps(one, 1, nullptr, every, st, /*tune=*/false)

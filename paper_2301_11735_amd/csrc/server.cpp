@@ -285,7 +285,10 @@ int lat_server_step(lat_server *s, int32_t *n_finished)
         if (!big.empty()) {
             // a new chunk on the second stream: nothing to wait for, since a
             // lattice's set-up synchronised before it became resident
-            rc = enqueue_offchip_sweeps(big.data(), (int32_t)big.size(), big_sw.data(), 0, s->side);
+            // one launch per phase: a cooperative launch beside the on-chip
+            // kernels of the first stream could wait for compute units
+            rc = enqueue_offchip_sweeps(big.data(), (int32_t)big.size(), big_sw.data(), 0, s->side,
+                                        /*convert=*/true, /*persistent=*/false);
             if (rc) return rc;
             const hipError_t e = hipEventRecord(s->chunk_done[s->chunks_queued % kSideChunks], s->side);
             if (e != hipSuccess) return hip_fail(e, "lat_server_step");

@@ -78,10 +78,10 @@ __device__ __forceinline__ void grid_barrier_coherent(unsigned *counter, unsigne
     __syncthreads();
     if (threadIdx.x == 0) {
         __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned polls = 0;
+        const long long t0 = wall_clock64();
         while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
-            if (++polls > (1u << 24)) {
+            if (wall_clock64() - t0 > kBarrierTimeoutTicks) {
                 atomicOr(err, 1u);
                 break;
             }

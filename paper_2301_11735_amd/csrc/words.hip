@@ -56,24 +56,31 @@ __global__ void __launch_bounds__(kWordsThreads) k_phase_words(WordsArgs a)
     block_reduce_add<3>(tr, (unsigned long long *)(scr + kScrSlots) + 3 * (size_t)b);
 }
 
-// Persistent form: the sweeps of a whole call, or a whole observation
-// series, of one lattice in one launch of co-resident blocks (cooperative
-// launch).  Tables are staged once; every phase is one grid-stride pass over
-// the a-word tasks followed by a device-wide barrier.  All lattice words are
-// read and written at device coherence, so the barrier needs no cache
-// write-back or invalidation (measured on MI355X with 128 blocks: 2.3 us a
-// barrier, against 6.9 us with one release/acquire fence pair per block and
-// 12-14 us with a fence pair in every wave).  With records, after
-// every `every` sweeps the blocks reduce the lattice's observables into that
-// interval's record (pre-set to the tracker total before the series, the
-// sums zero) and add their tracker moves so far, then meet at one more
-// barrier, since the next phase writes what that pass reads.
+// Persistent form: the sweeps of a whole call of up to kWordsBatch lattices,
+// or a whole observation series of one lattice, in one launch of
+// co-resident blocks (cooperative launch); blocks first_block[i] ..
+// first_block[i+1]-1 update lattice i.  Tables are staged once; every phase
+// is one grid-stride pass over each lattice's a-word tasks by its own blocks,
+// followed by a device-wide barrier of all blocks.  Sweep it of the launch
+// (interval k, sweep e of it: it = k every + e) is sweep next_sweep + it of
+// every lattice with sweeps[i] > it; the blocks of the others only meet the
+// barriers.  All lattice words are read and written at device coherence, so
+// the barrier needs no cache write-back or invalidation (measured on MI355X
+// with 128 blocks: 2.3 us a barrier, against 6.9 us with one release/acquire
+// fence pair per block and 12-14 us with a fence pair in every wave).  With
+// records (one lattice), after every `every` sweeps the blocks reduce the
+// lattice's observables into that interval's record (pre-set to the tracker
+// total before the series, the sums zero) and add their tracker moves so
+// far, then meet at one more barrier, since the next phase writes what that
+// pass reads.
 template <int Q>
 __global__ void __launch_bounds__(kWordsThreads) k_words_series(WordsSeriesArgs a)
 {
     __shared__ uint2 s_tab[kDevTabEntries];
     __shared__ uint4 s_transd[kTransEntries];
-    uint8_t *scr = a.scratch;
+    int li = 0;  // this block's lattice (uniform)
+    while (li + 1 < a.count && blockIdx.x >= a.first_block[li + 1]) ++li;
+    uint8_t *scr = a.scratch[li];
     const LatDesc d = *(const LatDesc *)(scr + kScrDesc);
     uint32_t *st = d.enc == 1 ? (uint32_t *)d.state : (uint32_t *)(scr + kScrWork);
     {
@@ -83,23 +90,28 @@ __global__ void __launch_bounds__(kWordsThreads) k_words_series(WordsSeriesArgs 
         for (int i = threadIdx.x; i < kTransEntries; i += kWordsThreads) s_transd[i] = g_transd[i];
     }
     __syncthreads();
-    unsigned *counter = (unsigned *)(scr + kScrBarrier), *err = (unsigned *)(scr + kScrErr);
+    unsigned *counter = (unsigned *)(a.scratch[0] + kScrBarrier), *err = (unsigned *)(scr + kScrErr);
+    const uint32_t b = blockIdx.x - a.first_block[li], nb = a.first_block[li + 1] - a.first_block[li];
+    const uint32_t my_sweeps = a.sweeps[li];
     const uint32_t csz = (uint32_t)(d.L >> 1) * (uint32_t)(d.L >> 6);
-    const uint32_t n_tasks = (uint32_t)Q * csz, stride = gridDim.x * kWordsThreads;
-    const uint32_t first = blockIdx.x * kWordsThreads + threadIdx.x;
+    const uint32_t n_tasks = (uint32_t)Q * csz, stride = nb * kWordsThreads;
+    const uint32_t first = b * kWordsThreads + threadIdx.x;
     int tr[3] = {0, 0, 0};
     unsigned arrivals = 0;
     for (uint32_t k = 0; k < a.intervals; ++k) {
         for (uint32_t e = 0; e < a.every; ++e) {
-            const uint64_t s = d.next_sweep + (uint64_t)k * a.every + e;
+            const uint32_t it = k * a.every + e;
+            const uint64_t s = d.next_sweep + it;
             int r, mm[4], kk[4];
             device_schedule(d.L, d.key0, d.key1, s, r, mm, kk);
             for (int p = 0; p < 4; ++p) {
-                WordPhase f;
-                word_phase_setup(f, d.L, d.key0, d.key1, s, p, r, mm, kk);
-                // stride is a multiple of Q: a word's lanes are all in or all out
-                for (uint32_t t = first; t < n_tasks; t += stride)
-                    word_task<Q, false, false, true, true>(st, f, t, s_tab, s_transd, tr);
+                if (it < my_sweeps) {
+                    WordPhase f;
+                    word_phase_setup(f, d.L, d.key0, d.key1, s, p, r, mm, kk);
+                    // stride is a multiple of Q: a word's lanes are all in or all out
+                    for (uint32_t t = first; t < n_tasks; t += stride)
+                        word_task<Q, false, false, true, true>(st, f, t, s_tab, s_transd, tr);
+                }
                 arrivals += gridDim.x;
                 grid_barrier_coherent(counter, arrivals, err);
             }
@@ -111,16 +123,16 @@ __global__ void __launch_bounds__(kWordsThreads) k_words_series(WordsSeriesArgs 
             block_reduce_add<7>(v, rec + 3);
             long long t3[3] = {tr[0], tr[1], tr[2]};
             block_reduce_add<3>(t3, rec);
-            if (blockIdx.x == 0 && threadIdx.x == 0)
+            if (b == 0 && threadIdx.x == 0)
                 rec[10] = (unsigned long long)(d.next_sweep + (uint64_t)(k + 1) * a.every);
             arrivals += gridDim.x;
             grid_barrier_coherent(counter, arrivals, err);
         }
     }
-    block_reduce_add<3>(tr, (unsigned long long *)(scr + kScrSlots) + 3 * (size_t)blockIdx.x);
+    block_reduce_add<3>(tr, (unsigned long long *)(scr + kScrSlots) + 3 * (size_t)b);
     // every block read the descriptor before its first barrier
-    if (blockIdx.x == 0 && threadIdx.x == 0 && arrivals > 0)
-        ((LatDesc *)(scr + kScrDesc))->next_sweep = d.next_sweep + (uint64_t)a.intervals * a.every;
+    if (b == 0 && threadIdx.x == 0 && arrivals > 0)
+        ((LatDesc *)(scr + kScrDesc))->next_sweep = d.next_sweep + my_sweeps;
 }
 
 // Records of a series before it runs: the tracker total so far (slots and
@@ -253,7 +265,7 @@ const void *series_fn_of(int Q)
 }
 }  // namespace
 
-int words_series_grid(int L, int Q)
+int words_persistent_capacity(int Q)
 {
     int dev = 0, coop = 0, per_cu = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -262,27 +274,24 @@ int words_series_grid(int L, int Q)
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, series_fn_of(Q), kWordsThreads, 0) != hipSuccess ||
         per_cu < 1)
         return 0;
-    // one task per thread where the chip holds them, but no more blocks than
-    // tracker slots and no more than one per compute unit: fewer blocks make
-    // the device-wide barrier cheaper
-    uint32_t want = words_blocks(L, Q);
-    want = std::min<uint32_t>(want, (uint32_t)std::min(per_cu * cus, cus));
-    return (int)std::min<uint32_t>(want, (uint32_t)kMaxSlots);
+    return per_cu * cus;
 }
 
-hipError_t launch_words_series(const WordsSeriesArgs &a, int Q, int grid, hipStream_t s)
+hipError_t launch_words_series(const WordsSeriesArgs &a, int Q, hipStream_t s)
 {
-    hipError_t e = launch_zero_i64((unsigned long long *)(a.scratch + kScrBarrier), 1, s);  // barrier counter
+    // the launch's barrier counter lives in the first lattice's scratch
+    hipError_t e = launch_zero_i64((unsigned long long *)(a.scratch[0] + kScrBarrier), 1, s);
     if (e != hipSuccess) return e;
     if (a.records) {
-        hipLaunchKernelGGL(k_series_init, dim3(1), dim3(256), 0, s, (const uint8_t *)a.scratch, a.records,
+        hipLaunchKernelGGL(k_series_init, dim3(1), dim3(256), 0, s, (const uint8_t *)a.scratch[0], a.records,
                            a.intervals);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     WordsSeriesArgs args = a;
     void *kargs[] = {&args};
-    return hipLaunchCooperativeKernel(series_fn_of(Q), dim3(grid), dim3(kWordsThreads), kargs, 0, s);
+    return hipLaunchCooperativeKernel(series_fn_of(Q), dim3(a.first_block[a.count]), dim3(kWordsThreads), kargs, 0,
+                                      s);
 }
 
 hipError_t launch_advance_words(const WordsArgs &a, hipStream_t s)

@@ -22,7 +22,7 @@ with the drop).  drop_stats() measures a configuration on the host:
            antiferromagnetic order of the spins around the charge
 
 Usage:
-    python -m paper_2301_11735_amd.drop [--L 64] [--n 0.1] [--replicas 16] [--sweeps 4000] [--start neel|random]
+    python -m paper_2301_11735_amd.drop [--L 64] [--n 0.1] [--replicas 16] [--sweeps 20000] [--start neel|random]
 """
 from __future__ import annotations
 
@@ -46,7 +46,7 @@ LADDER = (1.2, 1.0, 0.8, 0.6, 0.5, 0.4, 0.3, 0.2, 0.15, 0.1)
 
 # Temperatures of the ladder for a start from the doped antiferromagnet: all
 # below the Neel temperature.
-NEEL_LADDER = (0.4, 0.3, 0.2, 0.15, 0.1)
+NEEL_LADDER = (0.4, 0.3, 0.2, 0.15, 0.12, 0.1, 0.08)
 
 
 def doped_neel(L: int, n_plus: int, n_minus: int, seed: int) -> np.ndarray:
@@ -163,7 +163,7 @@ CASES = (("J>>V", 1.0, 0.05), ("V>>J", 0.1, 1.0))
 DROP_DELTA = 3.0
 
 
-def run_cases(L: int = 64, n: float = 0.1, sweeps_per_T: int = 4000, replicas: int = 16, seed0: int = 1,
+def run_cases(L: int = 64, n: float = 0.1, sweeps_per_T: int = 20000, replicas: int = 16, seed0: int = 1,
               temps=NEEL_LADDER, start: str = "neel") -> list:
     Q, _ = lat.charge_target(L, n)
     out = []
@@ -180,7 +180,7 @@ def main():
     ap.add_argument("--L", type=int, default=64)
     ap.add_argument("--n", type=float, default=0.1)
     ap.add_argument("--replicas", type=int, default=16)
-    ap.add_argument("--sweeps", type=int, default=4000, help="sweeps per rung of the temperature ladder")
+    ap.add_argument("--sweeps", type=int, default=20000, help="sweeps per rung of the temperature ladder")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--start", choices=("neel", "random"), default="neel")
     args = ap.parse_args()

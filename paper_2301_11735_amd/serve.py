@@ -133,6 +133,10 @@ def main():
         "site_updates_per_s": updates / wall,
         "p50_s": percentile(lats, 50),
         "p99_s": percentile(lats, 99),
+        "by_L": {str(L): {"requests": len(v), "p50_s": percentile(v, 50), "p99_s": percentile(v, 99),
+                          "max_s": max(v)}
+                 for L in sorted({d["L"] for d in done.values()})
+                 for v in [[d["latency"] for d in done.values() if d["L"] == L]]},
         "steps": st.steps,
         "pool_mib": args.pool_mib,
         "slots": args.slots,

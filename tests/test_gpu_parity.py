@@ -225,11 +225,14 @@ def test_packed_int8_on_the_phase_kernel_matches_oracle(spec, monkeypatch):
     _run_parity(spec, [1, 3] if spec.L > 1024 else [1, 3, 10])
 
 
-def test_mixed_paths_in_one_batch_match_oracle():
+@pytest.mark.parametrize("persistent", ["1", "0"], ids=["persistent", "per-phase"])
+def test_mixed_paths_in_one_batch_match_oracle(persistent, monkeypatch):
     """One lattice_sweep_batch over lattices on all three paths (on-chip,
-    multi-block word kernel in one batched launch series, phase kernel):
-    every lattice bit-exact against its own oracle run."""
-    _say("case mixed paths")
+    multi-block word kernel -- one persistent launch for all its lattices, or
+    one launch per phase --, phase kernel): every lattice bit-exact against
+    its own oracle run."""
+    monkeypatch.setenv("LATTICE_WORDS_PERSISTENT", persistent)
+    _say(f"case mixed paths, persistent={persistent}")
     rng = np.random.default_rng(9)
     specs = []
     for i, (L, enc) in enumerate([(64, 1), (100, 0), (320, 1), (512, 0), (576, 1), (1024, 1), (516, 0)]):
