@@ -109,7 +109,12 @@ struct PhaseArgs {
     int p, r, m, k;
     uint32_t key0, key1;
     uint32_t s_lo, s_hi;
+    uint32_t magicW;  // ceil(2^32 / W) for W = L/64 words per class row (0 when W = 1)
 };
+// ceil(2^32 / W): umulhi(n, it) equals n / W (rounded down) whenever
+// n (it W - 2^32) < 2^32, in particular for thread indices n < 1024 at any
+// W < 2^22.
+inline uint32_t magic_div(uint32_t W) { return W <= 1 ? 0u : (uint32_t)((0x100000000ull + W - 1u) / W); }
 
 // One phase of up to kWordsBatch lattices in the 2-bit class layout (int8
 // ones through their packed copy), spread over many blocks per lattice:

@@ -336,6 +336,7 @@ int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
     a.trans_d = (const uint4 *)(h->d_scratch + kScrTransD);
     a.track = (unsigned long long *)(h->d_scratch + kScrSlots);
     a.L = h->L;
+    a.magicW = magic_div((uint32_t)h->L >> 6);
     a.key0 = (uint32_t)h->seed;
     a.key1 = (uint32_t)(h->seed >> 32);
     const int enc = swept_enc(h);

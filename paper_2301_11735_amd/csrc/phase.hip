@@ -127,8 +127,8 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
     const uint2 *s_tab = s_tabs;
     const uint4 *s_transd = (const uint4 *)(s_tabs + kLdsTransD);
     const int L = a.L, W = L >> 6, H = L >> 1, Lq = L >> 2;
-    const int rr = threadIdx.x / W, j = threadIdx.x - rr * W;
-    const int n_groups = H / rows_per_block;
+    const int rr = W == 1 ? (int)threadIdx.x : (int)__umulhi(threadIdx.x, a.magicW), j = (int)threadIdx.x - rr * W;
+    const int n_groups = H >> __builtin_ctz((unsigned)rows_per_block);  // a power of two
     uint32_t *st = (uint32_t *)a.state;
     const uint32_t csz = (uint32_t)H * (uint32_t)W;  // words per class; N/16 < 2^32
     const int p = a.p;
@@ -239,7 +239,7 @@ __device__ __forceinline__ void phase_2bit(const PhaseArgs &a, int rows_per_bloc
     // Every word read is either never written in this phase or written only
     // by this block in the iteration that owns it, after its read.
     int g = blockIdx.x;
-    PairWords cur{};
+    PairWords cur;  // loaded before it is read
     if (Stage) {
         constexpr int kTot = kLdsTabPairs, kK = 2;  // two 16-byte loads a thread cover 512-thread blocks
         const int bd = rows_per_block * W;  // the block size of every launch of this form

@@ -14,23 +14,28 @@
 // still needs.  Blocks then end together, so a step is not held up by small
 // lattices doing many cheap sweeps.  The larger lattices (L = 512) take the
 // multi-block word kernel, spread over many compute units, on a second
-// stream that keeps its own pace: while fewer than kSideChunks of its chunks
-// are in flight, a step queues the next one, max(1, quantum /
-// kWordsSweepCostSites) sweeps of every such lattice in one launch per phase
-// (a sweep costs about kWordsSweepCostSites site-update times of the on-chip
-// kernel whatever their number, as the launches are latency-bound), and a
-// finished lattice is harvested once the chunk holding its last sweep has
-// completed.  Results are bit-identical to running the same
+// stream with its own host thread (the launches of a chunk cost the host about
+// 5 us each, and the caller's thread spends most of a step waiting on the
+// first stream): while fewer than kSideChunks of its chunks are in flight,
+// that thread queues the next one, max(1, quantum / kWordsSweepCostSites)
+// sweeps of every such lattice in one launch per phase (a sweep costs about
+// kWordsSweepCostSites site-update times of the on-chip kernel whatever their
+// number, as the launches are latency-bound), and a finished lattice is
+// harvested by a step once the chunk holding its last sweep has completed.  Results are bit-identical to running the same
 // request alone: a lattice's chain depends only on its parameters, seed and
 // sweep index.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -135,6 +140,15 @@ struct lat_server {
     hipStream_t side = nullptr;               // multi-block lattices advance here, beside the on-chip launch
     hipEvent_t chunk_done[kSideChunks] = {};  // recorded after chunk c in slot c % kSideChunks
     uint64_t chunks_queued = 0, chunks_done = 0;
+    // The second stream's own host thread, which enqueues its chunks while
+    // the caller's thread waits on the first stream.  mu guards everything
+    // below and the requests; the thread sleeps on cv when it has no work.
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stop = false;
+    int side_rc = LAT_OK;  // first error of the worker, returned by the next step
+    std::string side_msg;
     std::unique_ptr<PoolAllocator> alloc;
     std::deque<uint64_t> queue;
     std::vector<uint64_t> resident;
@@ -183,6 +197,102 @@ int admit(lat_server *s)
     return LAT_OK;
 }
 
+bool on_chip(const Request &r) { return r.h->path == kPathLds; }
+
+// The second stream's thread.  It keeps up to kSideChunks chunks in flight:
+// each holds max(1, quantum / kWordsSweepCostSites) more sweeps of every
+// resident multi-block lattice that still needs some, in one launch per
+// phase for all of them; a chunk's event marks it complete, and a lattice is
+// harvested by the caller's thread once the chunk with its last sweep is.
+void side_worker(lat_server *s)
+{
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (!s->stop) {
+        auto has_work = [&] {
+            for (uint64_t id : s->resident) {
+                const Request &r = *s->reqs[id];
+                if (!on_chip(r) && r.done < r.sweeps) return true;
+            }
+            return false;
+        };
+        // retire completed chunks; block (without the lock) on the oldest
+        // when every slot is taken or there is nothing new to queue
+        while (s->chunks_done < s->chunks_queued) {
+            hipEvent_t ev = s->chunk_done[s->chunks_done % kSideChunks];
+            hipError_t e;
+            if (s->chunks_queued - s->chunks_done >= (uint64_t)kSideChunks || !has_work()) {
+                lk.unlock();
+                e = hipEventSynchronize(ev);
+                lk.lock();
+            } else {
+                e = hipEventQuery(ev);
+                if (e == hipErrorNotReady) break;
+            }
+            if (e != hipSuccess) {
+                s->side_rc = hip_fail(e, "server second stream");
+                s->side_msg = lattice_last_error();
+                return;
+            }
+            ++s->chunks_done;
+        }
+        if (s->stop) break;
+        std::vector<lattice *> big;
+        std::vector<uint32_t> big_sw;
+        std::vector<Request *> big_reqs;
+        const uint64_t c = s->chunks_queued;  // index of the chunk built now
+        for (uint64_t id : s->resident) {
+            Request &r = *s->reqs[id];
+            if (on_chip(r) || r.done >= r.sweeps) continue;
+            const uint64_t N = (uint64_t)r.params.L * r.params.L;
+            const uint32_t k = std::min((uint32_t)std::max<uint64_t>(1, s->quantum / kWordsSweepCostSites),
+                                        r.sweeps - r.done);
+            big.push_back(r.h);
+            big_sw.push_back(k);
+            big_reqs.push_back(&r);
+            r.done += k;
+            if (r.done >= r.sweeps) r.last_chunk = c;
+            s->site_updates += N * k;
+        }
+        if (big.empty()) {
+            if (s->chunks_done == s->chunks_queued) s->cv.wait_for(lk, std::chrono::milliseconds(2));
+            continue;
+        }
+        lk.unlock();
+        // one launch per phase: a cooperative launch beside the on-chip
+        // kernels of the first stream could wait for compute units
+        int rc = enqueue_offchip_sweeps(big.data(), (int32_t)big.size(), big_sw.data(), 0, s->side,
+                                        /*convert=*/true, /*persistent=*/false);
+        std::string msg = rc ? lattice_last_error() : "";
+        if (rc == LAT_OK) {
+            const hipError_t e = hipEventRecord(s->chunk_done[c % kSideChunks], s->side);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "server second stream");
+                msg = lattice_last_error();
+            }
+        }
+        lk.lock();
+        if (rc) {
+            s->side_rc = rc;
+            s->side_msg = msg;
+            return;
+        }
+        s->chunks_queued = c + 1;
+    }
+}
+
+// The second stream, its events and its thread, made when a multi-block
+// lattice first becomes resident (called with mu held).
+int start_side(lat_server *s)
+{
+    if (s->side) return LAT_OK;
+    hipError_t e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
+    for (int i = 0; i < kSideChunks && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&s->chunk_done[i], hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "lat_server_step: second stream");
+    s->worker = std::thread(side_worker, s);
+    return LAT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -223,6 +333,7 @@ int lat_server_submit(lat_server *s, const lat_params *p, uint32_t sweeps, int32
         const int rc = validate_params(p, &Q, &Nc);
         if (rc) return rc;
         auto r = std::make_unique<Request>();
+        std::lock_guard<std::mutex> lk(s->mu);
         r->id = s->next_id++;
         r->params = *p;
         if (p->init_codes) r->init.assign(p->init_codes, p->init_codes + (size_t)p->L * p->L);
@@ -241,106 +352,88 @@ int lat_server_step(lat_server *s, int32_t *n_finished)
 {
     return guarded("lat_server_step", [&]() -> int {
         if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
+        if (n_finished) *n_finished = 0;
+        std::unique_lock<std::mutex> lk(s->mu);
+        if (s->side_rc) return fail(s->side_rc, s->side_msg);
         int rc = admit(s);
         if (rc) return rc;
-        if (n_finished) *n_finished = 0;
         if (s->resident.empty()) return LAT_OK;
-
         bool any_big = false;
-        for (uint64_t id : s->resident) any_big = any_big || s->reqs[id]->h->path != kPathLds;
-        if (any_big && !s->side) {
-            // the second stream and its events, made when first needed
-            hipError_t e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
-            for (int i = 0; i < kSideChunks && e == hipSuccess; ++i)
-                e = hipEventCreateWithFlags(&s->chunk_done[i], hipEventDisableTiming);
-            if (e != hipSuccess) return hip_fail(e, "lat_server_step: second stream");
+        for (uint64_t id : s->resident) any_big = any_big || !on_chip(*s->reqs[id]);
+        if (any_big) {
+            rc = start_side(s);
+            if (rc) return rc;
+            s->cv.notify_one();
         }
-        // chunks of the second stream seen complete
-        while (s->chunks_done < s->chunks_queued) {
-            const hipError_t q = hipEventQuery(s->chunk_done[s->chunks_done % kSideChunks]);
-            if (q == hipErrorNotReady) break;
-            if (q != hipSuccess) return hip_fail(q, "lat_server_step: second stream");
-            ++s->chunks_done;
-        }
-        const bool side_room = s->chunks_queued - s->chunks_done < (uint64_t)kSideChunks;
 
-        std::vector<lattice *> hs, big;
-        std::vector<uint32_t> sw, big_sw;
-        std::vector<Request *> big_reqs;
+        // the on-chip lattices: one batched launch on the server's stream
+        std::vector<lattice *> hs;
+        std::vector<uint32_t> sw;
         for (uint64_t id : s->resident) {
             Request &r = *s->reqs[id];
-            if (r.done >= r.sweeps) continue;  // all its sweeps are enqueued
-            const bool on_chip = r.h->path == kPathLds;
-            if (!on_chip && !side_room) continue;
+            if (!on_chip(r) || r.done >= r.sweeps) continue;
             const uint64_t N = (uint64_t)r.params.L * r.params.L;
-            const uint64_t cost = on_chip ? N + kSweepCostSites : kWordsSweepCostSites;
-            const uint32_t want = (uint32_t)std::max<uint64_t>(1, s->quantum / cost);
+            const uint32_t want = (uint32_t)std::max<uint64_t>(1, s->quantum / (N + kSweepCostSites));
             const uint32_t k = std::min(want, r.sweeps - r.done);
-            (on_chip ? hs : big).push_back(r.h);
-            (on_chip ? sw : big_sw).push_back(k);
-            if (!on_chip) big_reqs.push_back(&r);
+            hs.push_back(r.h);
+            sw.push_back(k);
             r.done += k;
             s->site_updates += N * k;
         }
-        if (!big.empty()) {
-            // a new chunk on the second stream: nothing to wait for, since a
-            // lattice's set-up synchronised before it became resident
-            // one launch per phase: a cooperative launch beside the on-chip
-            // kernels of the first stream could wait for compute units
-            rc = enqueue_offchip_sweeps(big.data(), (int32_t)big.size(), big_sw.data(), 0, s->side,
-                                        /*convert=*/true, /*persistent=*/false);
-            if (rc) return rc;
-            const hipError_t e = hipEventRecord(s->chunk_done[s->chunks_queued % kSideChunks], s->side);
-            if (e != hipSuccess) return hip_fail(e, "lat_server_step");
-            for (Request *r : big_reqs)
-                if (r->done >= r->sweeps) r->last_chunk = s->chunks_queued;
-            ++s->chunks_queued;
-        }
-        if (!hs.empty()) {
-            rc = enqueue_lds_sweeps(hs.data(), (int32_t)hs.size(), sw.data(), 0, s->stream);
-            if (rc) return rc;
-        }
-        if (!hs.empty() || !big.empty()) ++s->steps;
-
         // Harvest: on-chip lattices with all their sweeps enqueued (their
         // work is ordered before the harvest on the server's stream), and
         // multi-block ones once the chunk holding their last sweep has
-        // completed on the second stream.
+        // completed on the second stream (the worker no longer touches them).
         std::vector<lattice *> fin;
-        std::vector<uint64_t> fin_ids, keep;
+        std::vector<uint64_t> fin_ids;
+        std::vector<bool> fin_keep;
         for (uint64_t id : s->resident) {
-            Request &r = *s->reqs[id];
-            const bool ready =
-                r.done >= r.sweeps && (r.h->path == kPathLds || (r.last_chunk < s->chunks_done));
-            if (ready) {
+            const Request &r = *s->reqs[id];
+            if (r.done >= r.sweeps && (on_chip(r) || r.last_chunk < s->chunks_done)) {
                 fin.push_back(r.h);
                 fin_ids.push_back(id);
-            } else {
-                keep.push_back(id);
+                fin_keep.push_back(r.keep_state);
             }
         }
+        lk.unlock();
+
+        if (!hs.empty()) {
+            rc = enqueue_lds_sweeps(hs.data(), (int32_t)hs.size(), sw.data(), 0, s->stream);
+            if (rc) return rc;
+            ++s->steps;
+        }
+        std::vector<lat_obs> obs(fin.size());
+        std::vector<std::vector<int8_t>> codes(fin.size());
         if (!fin.empty()) {
-            std::vector<lat_obs> obs(fin.size());
             rc = lattice_observables_batch(fin.data(), (int32_t)fin.size(), s->pool + s->obs_off,
                                            (size_t)s->max_slots * 80u, obs.data(), s->stream);
             if (rc) return rc;
-            const double t = now_s();
             for (size_t i = 0; i < fin.size(); ++i) {
-                Request &r = *s->reqs[fin_ids[i]];
-                r.obs = obs[i];
-                if (r.keep_state) {
-                    r.final_codes.resize((size_t)r.params.L * r.params.L);
-                    rc = lattice_read_state(r.h, r.final_codes.data());
-                    if (rc) return rc;
-                }
-                lattice_destroy(r.h);
-                r.h = nullptr;
-                s->alloc->release(r.off, r.bytes);
-                r.status = LAT_REQ_FINISHED;
-                r.t_finish = t;
+                if (!fin_keep[i]) continue;
+                codes[i].resize((size_t)fin[i]->L * fin[i]->L);
+                rc = lattice_read_state(fin[i], codes[i].data());
+                if (rc) return rc;
             }
         }
-        s->resident = keep;
+
+        lk.lock();
+        const double t = now_s();
+        for (size_t i = 0; i < fin.size(); ++i) {
+            Request &r = *s->reqs[fin_ids[i]];
+            r.obs = obs[i];
+            r.final_codes = std::move(codes[i]);
+            lattice_destroy(r.h);
+            r.h = nullptr;
+            s->alloc->release(r.off, r.bytes);
+            r.status = LAT_REQ_FINISHED;
+            r.t_finish = t;
+        }
+        if (!fin.empty()) {
+            std::vector<uint64_t> keep;
+            for (uint64_t id : s->resident)
+                if (s->reqs[id]->status == LAT_REQ_RESIDENT) keep.push_back(id);
+            s->resident = keep;
+        }
         if (n_finished) *n_finished = (int32_t)fin.size();
         return LAT_OK;
     });
@@ -350,6 +443,7 @@ int lat_server_poll(lat_server *s, uint64_t id, lat_request_info *out, int8_t *f
 {
     return guarded("lat_server_poll", [&]() -> int {
         if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
+        std::lock_guard<std::mutex> lk(s->mu);
         auto it = s->reqs.find(id);
         if (it == s->reqs.end() || !out) return fail(LAT_EINVAL, "unknown request");
         const Request &r = *it->second;
@@ -374,6 +468,7 @@ int lat_server_release(lat_server *s, uint64_t id)
 {
     return guarded("lat_server_release", [&]() -> int {
         if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
+        std::lock_guard<std::mutex> lk(s->mu);
         auto it = s->reqs.find(id);
         if (it == s->reqs.end() ||
             (it->second->status != LAT_REQ_FINISHED && it->second->status != LAT_REQ_FAILED))
@@ -387,6 +482,7 @@ int lat_server_stats(lat_server *s, lat_server_counters *out)
 {
     return guarded("lat_server_stats", [&]() -> int {
         if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
+        std::lock_guard<std::mutex> lk(s->mu);
         if (!out) return fail(LAT_EINVAL, "null output");
         out->queued = (int32_t)s->queue.size();
         out->resident = (int32_t)s->resident.size();
@@ -401,6 +497,14 @@ int lat_server_destroy(lat_server *s)
 {
     return guarded("lat_server_destroy", [&]() -> int {
         if (!server_live(s)) return fail(LAT_ESTATE, "null or destroyed server");
+        if (s->worker.joinable()) {
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->stop = true;
+            }
+            s->cv.notify_one();
+            s->worker.join();
+        }
         hipError_t e = s->side ? hipStreamSynchronize(s->side) : hipSuccess;
         const hipError_t e2 = hipStreamSynchronize(s->stream);
         if (e == hipSuccess) e = e2;

@@ -92,3 +92,26 @@ def test_heat_capacity_curve_4x4_matches_exact():
         assert row["C_err"] < 0.3 * ex["C"], f"T={row['T']}: error bar {row['C_err']:.4f} too wide for C={ex['C']:.4f}"
         _close("C", row["C"], row["C_err"], ex["C"], row["T"])
         _close("e", row["e"], row["e_err"], e_ex, row["T"])
+
+
+def test_charge_collects_into_a_drop_when_exchange_dominates():
+    """Section 4's charge drop on a 64 x 64 lattice at n = 0.1 (410 charges of
+    one sign; Delta = 3 keeps +- pairs from forming), 16 replicas started from
+    a Neel antiferromagnet doped at random and cooled to T = 0.08: with
+    J >> V (J = 1, V = 0.05) the charge gathers into one compact cluster inside
+    an antiferromagnetic background; with V >> J (J = 0.1, V = 1) the like
+    charges stay apart.  The measures (largest charged cluster / charges,
+    charge-spin bonds per charge, staggered spin order) are pinned on the CPU
+    by tests/test_drop_stats.py."""
+    from paper_2301_11735_amd import drop
+
+    _say("case charge drop 64x64")
+    rows = {r["case"]: r for r in drop.run_cases(64, 0.1, 20000, 16, 1)}
+    jv, vj = rows["J>>V"], rows["V>>J"]
+    for r in (jv, vj):
+        _say(f"{r['case']}: drop {r['drop']:.3f} +- {r['drop_err']:.3f} (min {r['drop_min']:.3f}), "
+             f"perim {r['perim']:.3f}, af {r['af']:.4f}, clusters {r['clusters']:.1f}")
+    assert jv["drop"] > 0.75 and jv["drop_min"] > 0.5   # most of the charge in one cluster
+    assert jv["perim"] < 1.0                              # compact: few charge-spin bonds per charge
+    assert jv["af"] > 0.99                                # the rest stays antiferromagnetic
+    assert vj["drop_max"] < 0.01 and vj["perim"] > 3.9   # isolated charges
