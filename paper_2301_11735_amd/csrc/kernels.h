@@ -135,12 +135,15 @@ struct WordsArgs {
 // Lanes per a-word for side L (fewer for larger lattices, whose words fill
 // the chip anyway), and the blocks one lattice takes.
 int words_lanes(int L);
-inline uint32_t words_blocks(int L, int Q)
+inline uint32_t words_blocks(int L, int Q, int threads = kWordsThreads)
 {
     const uint32_t tasks = (uint32_t)Q * (uint32_t)L * (uint32_t)L / 128u;
-    return (tasks + kWordsThreads - 1) / kWordsThreads;
+    return (tasks + (uint32_t)threads - 1) / (uint32_t)threads;
 }
-hipError_t launch_phase_words(const WordsArgs &a, int Q, hipStream_t s);
+// Threads per block of the per-phase form: a multiple of 64 up to 1024
+// (every block stages the tables, so larger blocks stage them fewer times).
+constexpr int kWordsPhaseMaxThreads = 1024;
+hipError_t launch_phase_words(const WordsArgs &a, int Q, int threads, hipStream_t s);
 // desc->next_sweep += sweeps[i] for every lattice of the series.
 hipError_t launch_advance_words(const WordsArgs &a, hipStream_t s);
 // Persistent multi-block form: up to kWordsBatch lattices (blocks

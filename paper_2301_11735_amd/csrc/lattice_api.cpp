@@ -379,6 +379,15 @@ int enqueue_phase_sweeps(lattice *h, uint32_t sweeps, hipStream_t stream)
     return LAT_OK;
 }
 
+// Threads per block of the per-phase word kernel (LATTICE_WORDS_BLOCK: a
+// multiple of 64 up to 1024).
+int words_phase_threads()
+{
+    const char *v = std::getenv("LATTICE_WORDS_BLOCK");
+    const int want = v ? std::atoi(v) : 0;
+    return want >= 64 && want <= kWordsPhaseMaxThreads && want % 64 == 0 ? want : kWordsThreads;
+}
+
 // Multi-block word path: lattices in groups of up to kWordsBatch per launch,
 // one launch per phase of every sweep of the series (the lattice i of a
 // group skips the sweeps past sweeps[i]), then the device sweep counters
@@ -393,10 +402,11 @@ int enqueue_words_sweeps(lattice *const *hs, int32_t count, const uint32_t *swee
         int max_L = 0;
         for (int i = 0; i < a.count; ++i) max_L = std::max(max_L, hs[b + i]->L);
         const int Q = words_lanes(max_L);
+        const int threads = words_phase_threads();
         uint32_t blocks = 0, most = 0;
         for (int i = 0; i < a.count; ++i) {
             const lattice *h = hs[b + i];
-            const uint32_t nb = words_blocks(h->L, Q);
+            const uint32_t nb = words_blocks(h->L, Q, threads);
             if (nb > (uint32_t)kMaxSlots) return fail(LAT_EINVAL, "lattice too large for the multi-block word kernel");
             a.scratch[i] = h->d_scratch;
             a.sweeps[i] = sweeps ? sweeps[b + i] : uniform;
@@ -410,7 +420,7 @@ int enqueue_words_sweeps(lattice *const *hs, int32_t count, const uint32_t *swee
             a.iter = it;
             for (int p = 0; p < 4; ++p) {
                 a.p = p;
-                const hipError_t e = launch_phase_words(a, Q, stream);
+                const hipError_t e = launch_phase_words(a, Q, threads, stream);
                 if (e != hipSuccess) return hip_fail(e, "word phase kernel launch");
             }
         }
@@ -463,7 +473,16 @@ int enqueue_words_persistent(lattice *const *hs, int32_t count, const uint32_t *
     const char *v = std::getenv("LATTICE_WORDS_PERSISTENT");
     if (v ? std::atoi(v) == 0 : max_L > (records ? kWordsPersistentSeriesMaxL : kWordsPersistentMaxL)) return LAT_OK;
     if (records && count != 1) return fail(LAT_EINVAL, "an observation series holds one lattice");
-    const int Q = words_lanes(max_L);
+    // lanes per a-word: 8 up to L = 512 and 2 above.  This form's
+    // device-coherent loads set its pace, and fewer lanes per word load fewer
+    // words in all: at L = 1024 a sweep with its observables took 32.8, 36.7
+    // and 44.9 us with 2, 4 and 8 lanes; at L = 2048, 43 and 78 us with 2 and
+    // 4.  LATTICE_WORDS_LANES (1, 2, 4 or 8) overrides.
+    int Q = max_L <= 512 ? 8 : 2;
+    if (const char *q = std::getenv("LATTICE_WORDS_LANES")) {
+        const int want = std::atoi(q);
+        if (want == 1 || want == 2 || want == 4 || want == 8) Q = want;
+    }
     const int capacity = words_capacity(Q);
     if (capacity <= 0) return LAT_OK;
     // the barrier counter counts blocks x barriers: at most 2^20 barriers per

@@ -23,7 +23,7 @@ namespace lat {
 namespace {
 
 template <int Q>
-__global__ void __launch_bounds__(kWordsThreads) k_phase_words(WordsArgs a)
+__global__ void __launch_bounds__(kWordsPhaseMaxThreads) k_phase_words(WordsArgs a)
 {
     __shared__ uint2 s_tab[kDevTabEntries];
     __shared__ uint4 s_transd[kTransEntries];
@@ -37,8 +37,8 @@ __global__ void __launch_bounds__(kWordsThreads) k_phase_words(WordsArgs a)
     {
         const uint2 *g_tab = (const uint2 *)(scr + kScrDevTab);
         const uint4 *g_transd = (const uint4 *)(scr + kScrTransD);
-        for (int i = threadIdx.x; i < kDevTabEntries; i += kWordsThreads) s_tab[i] = g_tab[i];
-        for (int i = threadIdx.x; i < kTransEntries; i += kWordsThreads) s_transd[i] = g_transd[i];
+        for (int i = threadIdx.x; i < kDevTabEntries; i += blockDim.x) s_tab[i] = g_tab[i];
+        for (int i = threadIdx.x; i < kTransEntries; i += blockDim.x) s_transd[i] = g_transd[i];
     }
     const uint64_t s = d.next_sweep + a.iter;
     int r, mm[4], kk[4];
@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(kWordsThreads) k_phase_words(WordsArgs a)
     __syncthreads();
 
     const uint32_t b = blockIdx.x - a.first_block[li];
-    const uint32_t task = b * kWordsThreads + threadIdx.x;
+    const uint32_t task = b * blockDim.x + threadIdx.x;
     int tr[3] = {0, 0, 0};
     // tasks = Q * csz is a multiple of Q, so a word's lanes are all in or all out
     if (task < (uint32_t)Q * csz) word_task<Q, false, false, true>(st, f, task, s_tab, s_transd, tr);
@@ -236,9 +236,9 @@ int words_lanes(int L)
     return 1;
 }
 
-hipError_t launch_phase_words(const WordsArgs &a, int Q, hipStream_t s)
+hipError_t launch_phase_words(const WordsArgs &a, int Q, int threads, hipStream_t s)
 {
-    const dim3 grid(a.first_block[a.count]), block(kWordsThreads);
+    const dim3 grid(a.first_block[a.count]), block((unsigned)threads);
     switch (Q) {
     case 1: hipLaunchKernelGGL(k_phase_words<1>, grid, block, 0, s, a); break;
     case 2: hipLaunchKernelGGL(k_phase_words<2>, grid, block, 0, s, a); break;

@@ -18,7 +18,7 @@ hipError_t launch_phase_2bit(const PhaseArgs &, const Tuning2Bit &, hipStream_t)
 hipError_t launch_zero_i64(unsigned long long *, int, hipStream_t) { return hipSuccess; }
 hipError_t launch_observables(uint8_t *, const void *, int, int, hipStream_t, long long *) { return hipSuccess; }
 int words_lanes(int) { return 1; }
-hipError_t launch_phase_words(const WordsArgs &, int, hipStream_t) { return hipSuccess; }
+hipError_t launch_phase_words(const WordsArgs &, int, int, hipStream_t) { return hipSuccess; }
 hipError_t launch_advance_words(const WordsArgs &, hipStream_t) { return hipSuccess; }
 int words_persistent_capacity(int) { return 0; }
 hipError_t launch_words_series(const WordsSeriesArgs &, int, hipStream_t) { return hipSuccess; }

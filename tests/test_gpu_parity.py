@@ -200,15 +200,17 @@ def test_phase_kernel_path_matches_oracle(spec, monkeypatch):
     SMALL.with_(L=1024, encoding=1, n=0.3, T=0.4, seed=76),
     SMALL.with_(L=2048, encoding=1, T=1.7, seed=77),
 ], ids=lambda s: f"enc{s.encoding}-L{s.L}")
-@pytest.mark.parametrize("persistent", ["1", "0"], ids=["persistent", "per-phase"])
-def test_word_path_matches_oracle(spec, persistent, monkeypatch):
+@pytest.mark.parametrize("persistent,block", [("1", "256"), ("0", "256"), ("0", "1024")],
+                         ids=["persistent", "per-phase", "per-phase-1024"])
+def test_word_path_matches_oracle(spec, persistent, block, monkeypatch):
     """The multi-block word kernel (Q lanes per a-word, schedules computed on
     the device, several blocks per lattice) at every size it takes, both
     encodings, as one persistent launch per call (device-wide barriers
-    between phases) and as one launch per phase: the same chain as the
-    oracle, bit for bit."""
+    between phases) and as one launch per phase (blocks of 256 or 1024
+    threads): the same chain as the oracle, bit for bit."""
     monkeypatch.setenv("LATTICE_PATH", "words")
     monkeypatch.setenv("LATTICE_WORDS_PERSISTENT", persistent)
+    monkeypatch.setenv("LATTICE_WORDS_BLOCK", block)
     _run_parity(spec, [1, 3, 10] if spec.L <= 1024 else [1, 2])
 
 
