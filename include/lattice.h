@@ -133,9 +133,12 @@ int lattice_sweep(lattice *h, uint32_t sweeps);
 int lattice_observables(lattice *h, lat_obs *out);
 
 /* An observation series kept on the device: `intervals` times, advance the
- * lattice by `every` sweeps and reduce its observables (as
- * lattice_observables) into record k of d_series, with no host
- * synchronisation in between.  Record k is 88 bytes at byte 88k: 11 int64,
+ * lattice by `every` sweeps and write its observables (the values
+ * lattice_observables would return) into record k of d_series, with no host
+ * synchronisation in between.  Lattices on the persistent multi-block path
+ * take the records from the sums before the series plus the tracked moves
+ * (integers, equal to a reduction of the configuration); the others reduce
+ * the configuration after each interval.  Record k is 88 bytes at byte 88k: 11 int64,
  * the tracker (nD, nV, nJ), the 7 sums in lat_obs order from sum_S to
  * C_stag, and the sweep index after the interval (start_sweep + sweeps
  * done).  d_series is caller-owned device memory of at least 88*intervals

@@ -465,19 +465,22 @@ int enqueue_words_persistent(lattice *const *hs, int32_t count, const uint32_t *
     }
     // default: on up to L = 512 for plain sweeps, where it measured faster
     // than one launch per phase (13.6 against 21.9 us a sweep at L = 512);
-    // above, its device-coherent loads, which bypass the L2, cost more than
-    // the launches they save (27 against 24 us at L = 1024).  A series with
-    // its reductions every sweep measured 36.7 against 38.4 us a sweep at
-    // L = 1024 and needs one launch instead of seven per sweep, so series take
-    // it up to L = 1024.  LATTICE_WORDS_PERSISTENT=0|1 overrides.
+    // above, its device-coherent loads, which no compute unit's cache serves,
+    // cost more than the launches they save (25.6 against 24.7 us at
+    // L = 1024).  A series with observables every sweep takes its records from
+    // the tracked moves in this form (no pass over the lattice, no extra
+    // barrier): 26.9 us a sweep at L = 1024, against 34.6 us with launches
+    // per phase and a reduction launch per interval, so series take it up to
+    // L = 1024.  LATTICE_WORDS_PERSISTENT=0|1 overrides.
     const char *v = std::getenv("LATTICE_WORDS_PERSISTENT");
     if (v ? std::atoi(v) == 0 : max_L > (records ? kWordsPersistentSeriesMaxL : kWordsPersistentMaxL)) return LAT_OK;
     if (records && count != 1) return fail(LAT_EINVAL, "an observation series holds one lattice");
     // lanes per a-word: 8 up to L = 512 and 2 above.  This form's
     // device-coherent loads set its pace, and fewer lanes per word load fewer
-    // words in all: at L = 1024 a sweep with its observables took 32.8, 36.7
-    // and 44.9 us with 2, 4 and 8 lanes; at L = 2048, 43 and 78 us with 2 and
-    // 4.  LATTICE_WORDS_LANES (1, 2, 4 or 8) overrides.
+    // words in all: at L = 1024 a sweep with its observables took 26.9, 29.6
+    // and 35.5 us with 2, 4 and 8 lanes (at L = 512, 17-19 us with any of
+    // them); at L = 2048, 43 and 78 us with 2 and 4.  LATTICE_WORDS_LANES
+    // (1, 2, 4 or 8) overrides.
     int Q = max_L <= 512 ? 8 : 2;
     if (const char *q = std::getenv("LATTICE_WORDS_LANES")) {
         const int want = std::atoi(q);
@@ -488,7 +491,7 @@ int enqueue_words_persistent(lattice *const *hs, int32_t count, const uint32_t *
     // the barrier counter counts blocks x barriers: at most 2^20 barriers per
     // launch keeps it below 2^32 for any resident grid
     constexpr uint64_t kMaxBarriers = 1u << 20;
-    const uint64_t per_interval = 4ull * every + (records ? 1u : 0u);
+    const uint64_t per_interval = 4ull * every;
     if (per_interval > kMaxBarriers && records) return LAT_OK;  // such intervals take the per-phase launches
     const uint32_t sweeps_cap = (uint32_t)(kMaxBarriers / 4);
     const uint32_t intervals_cap = records ? (uint32_t)std::max<uint64_t>(1, kMaxBarriers / per_interval) : 1u;

@@ -119,6 +119,19 @@ __device__ __forceinline__ void word_phase_setup(WordPhase &f, int L, uint32_t k
     f.oBV = (uint32_t)f.pb * csz;
 }
 
+// Sum of the charges S and of the spins sigma of the 16 sites of a class
+// word (2-bit codes: 0 sigma = +1, 1 sigma = -1, 2 S = +1, 3 S = -1).
+__device__ __forceinline__ int charge_sum16(uint32_t w)
+{
+    const uint32_t h = (w >> 1) & kM5, l = w & kM5;
+    return __popc(h & ~l) - __popc(h & l);
+}
+__device__ __forceinline__ int spin_sum16(uint32_t w)
+{
+    const uint32_t h = (w >> 1) & kM5, l = w & kM5;
+    return __popc((h | l) ^ kM5) - __popc(l & ~h);
+}
+
 // Observable sums of class word i (16 sites) of a lattice of side L in the
 // 2-bit class layout: sum S, sum S^2, the S S and sigma sigma bonds to the
 // right and lower neighbours, sum sigma, and the staggered sums.  The right
@@ -140,8 +153,8 @@ __device__ __forceinline__ void obs_word_2bit(const uint32_t *st, int L, uint32_
     const uint32_t wd = cy == 0 ? ldw<Coh>(st, i + 4 * csz)
                                 : ldw<Coh>(st, (uint32_t)cx * csz + (uint32_t)(Y + 1 == H ? 0 : Y + 1) * W + j);
     const uint32_t h = (w >> 1) & kM5, l = w & kM5;
-    const int sumS = __popc(h & ~l) - __popc(h & l);
-    const int sumG = __popc((h | l) ^ kM5) - __popc(l & ~h);
+    const int sumS = charge_sum16(w);
+    const int sumG = spin_sum16(w);
     int bSS = 0, bss = 0;
     bond_sums(h, l, (wr >> 1) & kM5, wr & kM5, bSS, bss);
     bond_sums(h, l, (wd >> 1) & kM5, wd & kM5, bSS, bss);
@@ -202,11 +215,17 @@ __device__ __forceinline__ uint32_t task_call0(const WordPhase &f, uint32_t task
 // and applies the two b-word changes as atomics; one store and two atomics
 // per word instead of 3Q atomics.  Every lane of a word must be active.
 // Coh: the lattice words are read and written through ldw/stw<true>.
-template <int Q, bool Barrier, bool Pipe = false, bool Combine = false, bool Coh = false>
+// Obs (with Combine): the word's first lane also adds the changes of the
+// spin sum, the staggered spin sum and the staggered charge sum over the
+// word's a-sites and b-sites to dv[0..2] (the other observable sums are the
+// tracker's: the charged-site count and the two bond sums change by exactly
+// the accepted energy-change triples, and the charge sum does not change).
+template <int Q, bool Barrier, bool Pipe = false, bool Combine = false, bool Coh = false, bool Obs = false>
 __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uint32_t task, const uint2 *s_tab,
                                           const uint4 *s_transd, int (&tr)[3], u32x4 *pre = nullptr,
-                                          uint64_t ns = 0, int np = 0)
+                                          uint64_t ns = 0, int np = 0, int *dv = nullptr)
 {
+    static_assert(!Obs || Combine, "the observable moves are taken where a word's changes are combined");
     constexpr int LOGQ = Q == 1 ? 0 : Q == 2 ? 1 : Q == 4 ? 2 : 3;
     const uint32_t wi = task >> LOGQ;
     const int q = (int)(task & (uint32_t)(Q - 1));
@@ -355,6 +374,17 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
             cB |= lane_xor<4>(cB);
         }
         if (q == 0) {
+            if constexpr (Obs) {
+                // staggered sign of a class (cx, cy): (-1)^(cx + cy); the
+                // a-class is (p, 0), the b-class (pb, 1)
+                const int gA = spin_sum16(A0 ^ cA) - spin_sum16(A0), gB = spin_sum16(B0 ^ cB) - spin_sum16(B0);
+                const int sA = charge_sum16(A0 ^ cA) - charge_sum16(A0);
+                const int sB = charge_sum16(B0 ^ cB) - charge_sum16(B0);
+                const bool nA = f.p & 1, nB = !(f.pb & 1);
+                dv[0] += gA + gB;
+                dv[1] += (nA ? -gA : gA) + (nB ? -gB : gB);
+                dv[2] += (nA ? -sA : sA) + (nB ? -sB : sB);
+            }
             stw<Coh>(lat, f.oA0 + ro + j, A0 ^ cA);
             atomicXor(&lat[f.oB0 + rob + (uint32_t)jb], cB << (2 * shb));
             const uint32_t hi = shb ? cB >> (32 - 2 * shb) : 0u;

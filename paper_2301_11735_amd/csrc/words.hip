@@ -56,6 +56,26 @@ __global__ void __launch_bounds__(kWordsPhaseMaxThreads) k_phase_words(WordsArgs
     block_reduce_add<3>(tr, (unsigned long long *)(scr + kScrSlots) + 3 * (size_t)b);
 }
 
+// Adds the block's sums of m (per thread: tracker moves 0-2, spin,
+// staggered spin and staggered charge moves 3-5) to an observation record
+// (tracker 0-2, sums 3-9): m[0..2] to fields 0-2 and 4-6, m[3..5] to 7-9.
+__device__ __forceinline__ void add_record_moves(long long (&m)[6], unsigned long long *rec)
+{
+    __shared__ long long part[16][6];
+    wave_partials<6, long long>(m, part);
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        const int i = threadIdx.x < 6 ? (int)threadIdx.x % 3 : (int)threadIdx.x - 3;
+        const int field = threadIdx.x < 3 ? (int)threadIdx.x : (int)threadIdx.x + 1;
+        const int nw = kWordsThreads / 64;
+        long long sum = 0;
+#pragma unroll
+        for (int w = 0; w < nw; ++w) sum += part[w][i];
+        if (sum != 0) atomicAdd(&rec[field], (unsigned long long)sum);
+    }
+    __syncthreads();  // part is reused at the next interval
+}
+
 // Persistent form: the sweeps of a whole call of up to kWordsBatch lattices,
 // or a whole observation series of one lattice, in one launch of
 // co-resident blocks (cooperative launch); blocks first_block[i] ..
@@ -67,13 +87,17 @@ __global__ void __launch_bounds__(kWordsPhaseMaxThreads) k_phase_words(WordsArgs
 // barriers.  All lattice words are read and written at device coherence, so
 // the barrier needs no cache write-back or invalidation (measured on MI355X
 // with 128 blocks: 2.3 us a barrier, against 6.9 us with one release/acquire
-// fence pair per block and 12-14 us with a fence pair in every wave).  With
-// records (one lattice), after every `every` sweeps the blocks reduce the
-// lattice's observables into that interval's record (pre-set to the tracker
-// total before the series, the sums zero) and add their tracker moves so
-// far, then meet at one more barrier, since the next phase writes what that
-// pass reads.
-template <int Q>
+// fence pair per block and 12-14 us with a fence pair in every wave).
+//
+// Obs (a series with records, one lattice): the records start as the
+// lattice's state before the launch (k_series_init: tracker total and the
+// seven sums), and at the end of interval k every block adds its moves since
+// the launch began to record k: its tracker sums (to the tracker and to the
+// charged-site count and the two bond sums, which change by exactly them)
+// and the spin, staggered spin and staggered charge moves of the words it
+// wrote.  The lattice is not read for the records, so no barrier beyond the
+// phases' is needed; the records are whole when the launch ends.
+template <int Q, bool Obs>
 __global__ void __launch_bounds__(kWordsThreads) k_words_series(WordsSeriesArgs a)
 {
     __shared__ uint2 s_tab[kDevTabEntries];
@@ -97,6 +121,7 @@ __global__ void __launch_bounds__(kWordsThreads) k_words_series(WordsSeriesArgs 
     const uint32_t n_tasks = (uint32_t)Q * csz, stride = nb * kWordsThreads;
     const uint32_t first = b * kWordsThreads + threadIdx.x;
     int tr[3] = {0, 0, 0};
+    int dv[3] = {0, 0, 0};  // Obs: spin, staggered spin, staggered charge moves
     unsigned arrivals = 0;
     for (uint32_t k = 0; k < a.intervals; ++k) {
         for (uint32_t e = 0; e < a.every; ++e) {
@@ -110,23 +135,21 @@ __global__ void __launch_bounds__(kWordsThreads) k_words_series(WordsSeriesArgs 
                     word_phase_setup(f, d.L, d.key0, d.key1, s, p, r, mm, kk);
                     // stride is a multiple of Q: a word's lanes are all in or all out
                     for (uint32_t t = first; t < n_tasks; t += stride)
-                        word_task<Q, false, false, true, true>(st, f, t, s_tab, s_transd, tr);
+                        word_task<Q, false, false, true, true, Obs>(st, f, t, s_tab, s_transd, tr, nullptr, 0, 0, dv);
+                }
+                if constexpr (Obs) {
+                    if (p == 3 && e + 1 == a.every) {
+                        unsigned long long *rec =
+                            (unsigned long long *)(a.records + (kSeriesRecord / 8) * (size_t)k);
+                        long long m[6] = {tr[0], tr[1], tr[2], dv[0], dv[1], dv[2]};
+                        add_record_moves(m, rec);
+                        if (b == 0 && threadIdx.x == 0)
+                            rec[10] = (unsigned long long)(d.next_sweep + (uint64_t)(k + 1) * a.every);
+                    }
                 }
                 arrivals += gridDim.x;
                 grid_barrier_coherent(counter, arrivals, err);
             }
-        }
-        if (a.records) {
-            unsigned long long *rec = (unsigned long long *)(a.records + (kSeriesRecord / 8) * (size_t)k);
-            long long v[7] = {0, 0, 0, 0, 0, 0, 0};
-            for (uint32_t i = first; i < 8u * csz; i += stride) obs_word_2bit<true>(st, d.L, i, v);
-            block_reduce_add<7>(v, rec + 3);
-            long long t3[3] = {tr[0], tr[1], tr[2]};
-            block_reduce_add<3>(t3, rec);
-            if (b == 0 && threadIdx.x == 0)
-                rec[10] = (unsigned long long)(d.next_sweep + (uint64_t)(k + 1) * a.every);
-            arrivals += gridDim.x;
-            grid_barrier_coherent(counter, arrivals, err);
         }
     }
     block_reduce_add<3>(tr, (unsigned long long *)(scr + kScrSlots) + 3 * (size_t)b);
@@ -136,9 +159,12 @@ __global__ void __launch_bounds__(kWordsThreads) k_words_series(WordsSeriesArgs 
 }
 
 // Records of a series before it runs: the tracker total so far (slots and
-// base), the sums zero.
-__global__ void __launch_bounds__(256) k_series_init(const uint8_t *scr, long long *records, uint32_t intervals)
+// base) and the seven observable sums of the lattice's current state (its
+// 2-bit copy for an int8 lattice), in every record.  One block.
+__global__ void __launch_bounds__(1024) k_series_init(const uint8_t *scr, long long *records, uint32_t intervals)
 {
+    const LatDesc d = *(const LatDesc *)(scr + kScrDesc);
+    const uint32_t *st = d.enc == 1 ? (const uint32_t *)d.state : (const uint32_t *)(scr + kScrWork);
     long long t3[3] = {0, 0, 0};
     const long long *slots = (const long long *)(scr + kScrSlots);
     for (int i = threadIdx.x; i < kMaxSlots; i += blockDim.x) {
@@ -152,15 +178,17 @@ __global__ void __launch_bounds__(256) k_series_init(const uint8_t *scr, long lo
         t3[1] += base[1];
         t3[2] += base[2];
     }
-    __shared__ long long tot[3];
+    long long v[7] = {0, 0, 0, 0, 0, 0, 0};
+    const uint32_t n = 8u * (uint32_t)(d.L >> 1) * (uint32_t)(d.L >> 6);
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) obs_word_2bit(st, d.L, i, v);
+    __shared__ long long tot[10];
     block_reduce_store<3>(t3, tot);
+    block_reduce_store<7>(v, tot + 3);
     __syncthreads();
     for (uint32_t k = threadIdx.x; k < intervals; k += blockDim.x) {
         long long *rec = records + (kSeriesRecord / 8) * (size_t)k;
-        rec[0] = tot[0];
-        rec[1] = tot[1];
-        rec[2] = tot[2];
-        for (int q = 3; q < 11; ++q) rec[q] = 0;
+        for (int q = 0; q < 10; ++q) rec[q] = tot[q];
+        rec[10] = 0;
     }
 }
 
@@ -250,17 +278,17 @@ hipError_t launch_phase_words(const WordsArgs &a, int Q, int threads, hipStream_
 
 namespace {
 template <int Q>
-const void *series_fn()
+const void *series_fn(bool obs)
 {
-    return (const void *)k_words_series<Q>;
+    return obs ? (const void *)k_words_series<Q, true> : (const void *)k_words_series<Q, false>;
 }
-const void *series_fn_of(int Q)
+const void *series_fn_of(int Q, bool obs)
 {
     switch (Q) {
-    case 1: return series_fn<1>();
-    case 2: return series_fn<2>();
-    case 4: return series_fn<4>();
-    default: return series_fn<8>();
+    case 1: return series_fn<1>(obs);
+    case 2: return series_fn<2>(obs);
+    case 4: return series_fn<4>(obs);
+    default: return series_fn<8>(obs);
     }
 }
 }  // namespace
@@ -271,9 +299,14 @@ int words_persistent_capacity(int Q)
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, series_fn_of(Q), kWordsThreads, 0) != hipSuccess ||
-        per_cu < 1)
-        return 0;
+    // the smaller of the two forms' (with and without records) resident blocks
+    for (const bool obs : {false, true}) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, series_fn_of(Q, obs), kWordsThreads, 0) != hipSuccess ||
+            n < 1)
+            return 0;
+        per_cu = obs ? std::min(per_cu, n) : n;
+    }
     return per_cu * cus;
 }
 
@@ -283,15 +316,15 @@ hipError_t launch_words_series(const WordsSeriesArgs &a, int Q, hipStream_t s)
     hipError_t e = launch_zero_i64((unsigned long long *)(a.scratch[0] + kScrBarrier), 1, s);
     if (e != hipSuccess) return e;
     if (a.records) {
-        hipLaunchKernelGGL(k_series_init, dim3(1), dim3(256), 0, s, (const uint8_t *)a.scratch[0], a.records,
+        hipLaunchKernelGGL(k_series_init, dim3(1), dim3(1024), 0, s, (const uint8_t *)a.scratch[0], a.records,
                            a.intervals);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     WordsSeriesArgs args = a;
     void *kargs[] = {&args};
-    return hipLaunchCooperativeKernel(series_fn_of(Q), dim3(a.first_block[a.count]), dim3(kWordsThreads), kargs, 0,
-                                      s);
+    return hipLaunchCooperativeKernel(series_fn_of(Q, a.records != nullptr), dim3(a.first_block[a.count]),
+                                      dim3(kWordsThreads), kargs, 0, s);
 }
 
 hipError_t launch_advance_words(const WordsArgs &a, hipStream_t s)

@@ -561,7 +561,8 @@ def test_mid_series_per_phase_launches_match_oracle(monkeypatch):
     (SMALL.with_(L=100, seed=93), 2, 5),                           # int8 with L % 64 != 0
     (SMALL.with_(L=576, encoding=1, seed=94), 3, 4),               # words path, 2-bit, 9 words per class row
     (SMALL.with_(L=2048, encoding=1, T=0.7, seed=95), 1, 2),       # words path, Q = 2
-], ids=["mid", "lds", "phase-int8", "int8-L100", "words-L576", "words-L2048"])
+    (SMALL.with_(L=320, encoding=0, T=0.9, seed=96), 2, 5),        # words path, Q = 8, packed int8, 5 words a row
+], ids=["mid", "lds", "phase-int8", "int8-L100", "words-L576", "words-L2048", "words-L320"])
 @pytest.mark.parametrize("persistent", ["1", "0"], ids=["persistent", "per-phase"])
 def test_device_observation_series_matches_oracle(spec, every, intervals, persistent, monkeypatch):
     """lattice_sweep_series keeps the observables of every interval on the
