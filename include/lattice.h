@@ -117,7 +117,7 @@ int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void 
 /* Advance by `sweeps` sweeps (section 3.1 update, section 3.2 parallel form):
  * each sweep is four phases of N/8 non-interacting coupled pairs, so every
  * site is updated once per sweep.  Asynchronous on the handle's stream.
- * Lattices with L % 64 == 0 and 256 < L <= 512 advance in one cooperative
+ * Lattices with L % 64 == 0 and 256 < L <= 1024 advance in one cooperative
  * launch per call, whose blocks must all be resident at once, with a
  * device-wide barrier after every phase: kernels of other streams running
  * at the same time can delay it, and a barrier that waits longer than about
@@ -158,9 +158,12 @@ int lattice_read_state(lattice *h, int8_t *host_codes);
 /* Advance `count` lattices by `sweeps` sweeps each, on hip_stream (section
  * 3.2: several lattice copies processed together).  Lattices may differ in
  * L, encoding, parameters and seed; results are identical to calling
- * lattice_sweep on each.  Lattices with L <= 512 advance together in one
- * launch per 256 of them, each resident in on-chip memory for all the sweeps;
- * larger ones are advanced one after another.  The caller orders hip_stream
+ * lattice_sweep on each.  Lattices on the on-chip path (L <= 256 with
+ * L % 64 == 0, L <= 512 otherwise) advance together in one launch per 256 of
+ * them, each resident in on-chip memory for all the sweeps; those with
+ * L % 64 == 0 up to 2048 advance together on the multi-block word kernel (one
+ * cooperative launch per 64 of them up to L = 1024, as lattice_sweep, else
+ * one launch per phase); larger ones one after another.  The caller orders hip_stream
  * after any pending work of the lattices' own streams.  A lattice may appear
  * only once.  Errors: LAT_EINVAL, LAT_ESTATE, LAT_EHIP. */
 int lattice_sweep_batch(lattice *const *hs, int32_t count, uint32_t sweeps, void *hip_stream);

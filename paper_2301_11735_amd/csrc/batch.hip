@@ -210,8 +210,8 @@ __device__ __forceinline__ void word_sweeps(uint32_t *lat, uint32_t *sched, cons
             }
             if (pipe) {
                 if (threadIdx.x < tasks)
-                    word_task<Q, Barrier, true>(lat, f, threadIdx.x, s_tab, s_transd, tr, pre, p < 3 ? s : s + 1,
-                                                p < 3 ? p + 1 : 0);
+                    word_task<Q, Barrier, kDrawPipe>(lat, f, threadIdx.x, s_tab, s_transd, tr, pre,
+                                                     p < 3 ? s : s + 1, p < 3 ? p + 1 : 0);
             } else {
                 for (uint32_t t = threadIdx.x; t < tasks; t += blockDim.x)
                     word_task<Q, Barrier>(lat, f, t, s_tab, s_transd, tr);

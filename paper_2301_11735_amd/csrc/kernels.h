@@ -156,6 +156,7 @@ hipError_t launch_advance_words(const WordsArgs &a, hipStream_t s);
 // kernels enqueued first.
 struct WordsSeriesArgs {
     int count;
+    int threads;  // block size: a multiple of 64 up to kWordsThreads
     uint32_t intervals, every;
     long long *records;  // null: no observables
     uint8_t *scratch[kWordsBatch];
@@ -165,7 +166,7 @@ struct WordsSeriesArgs {
 // Blocks of the persistent launch that can be resident at once (0 when
 // co-residency cannot be guaranteed: no cooperative launch); the caller then
 // uses the per-phase launches.
-int words_persistent_capacity(int Q);
+int words_persistent_capacity(int Q, int threads);
 hipError_t launch_words_series(const WordsSeriesArgs &a, int Q, hipStream_t s);
 // int8 codes (row-major) <-> the 2-bit class layout, for L % 64 == 0.
 hipError_t launch_pack_int8(const int8_t *src, uint32_t *dst, int L, hipStream_t s);

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <cmath>
 #include <cstdint>
@@ -433,22 +434,35 @@ int enqueue_words_sweeps(lattice *const *hs, int32_t count, const uint32_t *swee
 
 }  // namespace
 
-constexpr int kWordsPersistentMaxL = 512, kWordsPersistentSeriesMaxL = 1024;
+constexpr int kWordsPersistentMaxL = 1024;
 
 namespace {
 
 // Resident-block capacity of the persistent word kernel per (device, Q),
 // looked up once.
-int words_capacity(int Q)
+int words_capacity(int Q, int threads)
 {
     static std::mutex mu;
-    static std::map<std::pair<int, int>, int> cache;
+    static std::map<std::tuple<int, int, int>, int> cache;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     std::lock_guard<std::mutex> lock(mu);
-    auto it = cache.find({dev, Q});
-    if (it == cache.end()) it = cache.emplace(std::make_pair(dev, Q), words_persistent_capacity(Q)).first;
+    const auto key = std::make_tuple(dev, Q, threads);
+    auto it = cache.find(key);
+    if (it == cache.end()) it = cache.emplace(key, words_persistent_capacity(Q, threads)).first;
     return it->second;
+}
+
+// Block size of the persistent word kernel: 256 threads unless
+// LATTICE_WORDS_SERIES_BLOCK asks for another multiple of 64 up to 256
+// (smaller blocks spread a lattice over more compute units).
+int words_series_threads()
+{
+    if (const char *v = std::getenv("LATTICE_WORDS_SERIES_BLOCK")) {
+        const int want = std::atoi(v);
+        if (want >= 64 && want <= kWordsThreads && want % 64 == 0) return want;
+    }
+    return kWordsThreads;
 }
 
 }  // namespace
@@ -463,30 +477,32 @@ int enqueue_words_persistent(lattice *const *hs, int32_t count, const uint32_t *
         if (hs[i]->path != kPathWords) return LAT_OK;
         max_L = std::max(max_L, hs[i]->L);
     }
-    // default: on up to L = 512 for plain sweeps, where it measured faster
-    // than one launch per phase (13.6 against 21.9 us a sweep at L = 512);
-    // above, its device-coherent loads, which no compute unit's cache serves,
-    // cost more than the launches they save (25.6 against 24.7 us at
-    // L = 1024).  A series with observables every sweep takes its records from
-    // the tracked moves in this form (no pass over the lattice, no extra
-    // barrier): 26.9 us a sweep at L = 1024, against 34.6 us with launches
-    // per phase and a reduction launch per interval, so series take it up to
-    // L = 1024.  LATTICE_WORDS_PERSISTENT=0|1 overrides.
+    // default: on up to L = 1024, where it measured faster than one launch
+    // per phase (13.2 against 21.9 us a sweep at L = 512, 23.0 against
+    // 24.7 us at L = 1024); above, its device-coherent loads, which no
+    // compute unit's cache serves, cost more than the launches they save
+    // (43 against 28 us at L = 2048).  A series with observables every sweep
+    // takes its records from the tracked moves in this form (no pass over
+    // the lattice, no extra barrier): 25.6 us a sweep at L = 1024, against
+    // 34.6 us with launches per phase and a reduction launch per interval.
+    // LATTICE_WORDS_PERSISTENT=0|1 overrides.
     const char *v = std::getenv("LATTICE_WORDS_PERSISTENT");
-    if (v ? std::atoi(v) == 0 : max_L > (records ? kWordsPersistentSeriesMaxL : kWordsPersistentMaxL)) return LAT_OK;
+    if (v ? std::atoi(v) == 0 : max_L > kWordsPersistentMaxL) return LAT_OK;
     if (records && count != 1) return fail(LAT_EINVAL, "an observation series holds one lattice");
     // lanes per a-word: 8 up to L = 512 and 2 above.  This form's
     // device-coherent loads set its pace, and fewer lanes per word load fewer
     // words in all: at L = 1024 a sweep with its observables took 26.9, 29.6
     // and 35.5 us with 2, 4 and 8 lanes (at L = 512, 17-19 us with any of
     // them); at L = 2048, 43 and 78 us with 2 and 4.  LATTICE_WORDS_LANES
-    // (1, 2, 4 or 8) overrides.
+    // (1, 2, 4 or 8) overrides.  Blocks of 256 threads: 128 and 64 measured
+    // slower at L = 512 and 1024 (more blocks meet at every barrier).
     int Q = max_L <= 512 ? 8 : 2;
     if (const char *q = std::getenv("LATTICE_WORDS_LANES")) {
         const int want = std::atoi(q);
         if (want == 1 || want == 2 || want == 4 || want == 8) Q = want;
     }
-    const int capacity = words_capacity(Q);
+    const int threads = words_series_threads();
+    const int capacity = words_capacity(Q, threads);
     if (capacity <= 0) return LAT_OK;
     // the barrier counter counts blocks x barriers: at most 2^20 barriers per
     // launch keeps it below 2^32 for any resident grid
@@ -504,7 +520,7 @@ int enqueue_words_persistent(lattice *const *hs, int32_t count, const uint32_t *
         uint32_t nb[kWordsBatch];
         uint32_t total = 0;
         for (int32_t i = 0; i < n; ++i) {
-            nb[i] = std::min<uint32_t>({words_blocks(hs[g0 + i]->L, Q), share, (uint32_t)kMaxSlots});
+            nb[i] = std::min<uint32_t>({words_blocks(hs[g0 + i]->L, Q, threads), share, (uint32_t)kMaxSlots});
             total += nb[i];
         }
         if (total > (uint32_t)capacity) return *ran ? fail(LAT_EHIP, "persistent word launch does not fit") : LAT_OK;
@@ -513,6 +529,7 @@ int enqueue_words_persistent(lattice *const *hs, int32_t count, const uint32_t *
             for (uint32_t k = 0; k < intervals; k += intervals_cap) {
                 WordsSeriesArgs a{};
                 a.count = 1;
+                a.threads = threads;
                 a.intervals = std::min(intervals_cap, intervals - k);
                 a.every = every;
                 a.records = records + (kSeriesRecord / 8) * (size_t)k;
@@ -532,6 +549,7 @@ int enqueue_words_persistent(lattice *const *hs, int32_t count, const uint32_t *
         for (int32_t i = 0; i < n; ++i) most = std::max(most, sweeps ? sweeps[g0 + i] : every);
         for (uint32_t c = 0; c < most; c += sweeps_cap) {
             WordsSeriesArgs a{};
+            a.threads = threads;
             a.intervals = 1;
             a.every = 0;
             uint32_t blocks = 0;

@@ -67,17 +67,22 @@ __device__ __forceinline__ uint32_t ld16(const uint32_t *st, uint32_t row, int W
 }
 
 // Device-wide barrier for kernels whose lattice words are all accessed at
-// device coherence (ldw/stw<true> and device-scope atomics): every wave
-// waits for its own memory operations to complete, the block meets, one
-// thread arrives on the monotonic counter and waits for the others; no
-// cache write-back or invalidation is needed.  The wait is bounded as in
-// grid_barrier (time-out flag, then go on).
-__device__ __forceinline__ void grid_barrier_coherent(unsigned *counter, unsigned target, unsigned *err)
+// device coherence (ldw/stw<true> and device-scope atomics), in two halves.
+// Arrive: every wave waits for its own memory operations to complete, the
+// block meets, and one thread arrives on the monotonic counter.  Wait: that
+// thread waits for the others, and the block meets again.  No cache
+// write-back or invalidation is needed.  Between the halves a block may do
+// work that touches no lattice word.  The wait is bounded as in grid_barrier
+// (time-out flag, then go on).
+__device__ __forceinline__ void grid_arrive_coherent(unsigned *counter)
 {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void grid_wait_coherent(unsigned *counter, unsigned target, unsigned *err)
+{
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const long long t0 = wall_clock64();
         while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
@@ -88,6 +93,11 @@ __device__ __forceinline__ void grid_barrier_coherent(unsigned *counter, unsigne
         }
     }
     __syncthreads();
+}
+__device__ __forceinline__ void grid_barrier_coherent(unsigned *counter, unsigned target, unsigned *err)
+{
+    grid_arrive_coherent(counter);
+    grid_wait_coherent(counter, target, err);
 }
 
 // The fields of WordPhase for phase p of a sweep with schedule (r, m, k), on
@@ -206,9 +216,11 @@ __device__ __forceinline__ uint32_t task_call0(const WordPhase &f, uint32_t task
     return (uint32_t)Y * (uint32_t)(f.Lq >> 1) + 8u * (uint32_t)j;
 }
 
-// Pipe: the task's draws for this phase are given in pre[], and those of the
-// next phase (sweep ns, phase np) are computed here, between the phase's
-// dependent LDS lookups, and returned in pre[].
+// Pipe (where the task's Philox draws come from): kDrawInPlace, computed
+// here as they are used; kDrawPipe, this phase's given in pre[] and those of
+// the next phase (sweep ns, phase np) computed here, between the phase's
+// dependent LDS lookups, and returned in pre[]; kDrawGiven, this phase's
+// given in pre[] (the caller makes the next phase's elsewhere).
 // Combine (lattice in global memory): the Q lanes of a word first OR their
 // code changes together (their fields are disjoint), then the word's first
 // lane stores the a-word, which no other word reads or writes in the phase,
@@ -220,7 +232,8 @@ __device__ __forceinline__ uint32_t task_call0(const WordPhase &f, uint32_t task
 // word's a-sites and b-sites to dv[0..2] (the other observable sums are the
 // tracker's: the charged-site count and the two bond sums change by exactly
 // the accepted energy-change triples, and the charge sum does not change).
-template <int Q, bool Barrier, bool Pipe = false, bool Combine = false, bool Coh = false, bool Obs = false>
+constexpr int kDrawInPlace = 0, kDrawPipe = 1, kDrawGiven = 2;
+template <int Q, bool Barrier, int Pipe = kDrawInPlace, bool Combine = false, bool Coh = false, bool Obs = false>
 __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uint32_t task, const uint2 *s_tab,
                                           const uint4 *s_transd, int (&tr)[3], u32x4 *pre = nullptr,
                                           uint64_t ns = 0, int np = 0, int *dv = nullptr)
@@ -295,7 +308,7 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
     uint32_t dlo = 0u, dhi = 0u, packed = 0u;
     const uint32_t kq2w = word_kq2(A0, B0);
     u32x4 nxt[kTaskCalls<Q>];
-    if constexpr (Pipe) {
+    if constexpr (Pipe == kDrawPipe) {
 #pragma unroll
         for (int i = 0; i < kTaskCalls<Q>; ++i)
             nxt[i] = philox4x32_10((uint32_t)ns, (uint32_t)np, call0 + (uint32_t)call_of_task<Q>(q, i),
@@ -303,7 +316,8 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
     }
     auto do_call = [&](int i, int c, uint32_t be, uint32_t bo, uint32_t &dacc) {
         const u32x4 w =
-            Pipe ? pre[i] : philox4x32_10(f.s_lo, (uint32_t)f.p, call0 + (uint32_t)c, f.s_hi, f.key0, f.key1);
+            Pipe != kDrawInPlace ? pre[i]
+                                 : philox4x32_10(f.s_lo, (uint32_t)f.p, call0 + (uint32_t)c, f.s_hi, f.key0, f.key1);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int t = 2 * c + h;
@@ -353,7 +367,7 @@ __device__ __forceinline__ void word_task(uint32_t *lat, const WordPhase &f, uin
     }
     const uint32_t dA = __builtin_amdgcn_perm(dhi, dlo, 0x05040100u);
     const uint32_t dB = __builtin_amdgcn_perm(dhi, dlo, 0x07060302u);
-    if constexpr (Pipe) {
+    if constexpr (Pipe == kDrawPipe) {
 #pragma unroll
         for (int i = 0; i < kTaskCalls<Q>; ++i) pre[i] = nxt[i];
     }

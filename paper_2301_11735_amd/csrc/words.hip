@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(kWordsPhaseMaxThreads) k_phase_words(WordsArgs
     const uint32_t task = b * blockDim.x + threadIdx.x;
     int tr[3] = {0, 0, 0};
     // tasks = Q * csz is a multiple of Q, so a word's lanes are all in or all out
-    if (task < (uint32_t)Q * csz) word_task<Q, false, false, true>(st, f, task, s_tab, s_transd, tr);
+    if (task < (uint32_t)Q * csz) word_task<Q, false, kDrawInPlace, true>(st, f, task, s_tab, s_transd, tr);
     block_reduce_add<3>(tr, (unsigned long long *)(scr + kScrSlots) + 3 * (size_t)b);
 }
 
@@ -67,9 +67,8 @@ __device__ __forceinline__ void add_record_moves(long long (&m)[6], unsigned lon
     if (threadIdx.x < 9) {
         const int i = threadIdx.x < 6 ? (int)threadIdx.x % 3 : (int)threadIdx.x - 3;
         const int field = threadIdx.x < 3 ? (int)threadIdx.x : (int)threadIdx.x + 1;
-        const int nw = kWordsThreads / 64;
+        const int nw = (int)(blockDim.x >> 6);
         long long sum = 0;
-#pragma unroll
         for (int w = 0; w < nw; ++w) sum += part[w][i];
         if (sum != 0) atomicAdd(&rec[field], (unsigned long long)sum);
     }
@@ -110,16 +109,37 @@ __global__ void __launch_bounds__(kWordsThreads) k_words_series(WordsSeriesArgs 
     {
         const uint2 *g_tab = (const uint2 *)(scr + kScrDevTab);
         const uint4 *g_transd = (const uint4 *)(scr + kScrTransD);
-        for (int i = threadIdx.x; i < kDevTabEntries; i += kWordsThreads) s_tab[i] = g_tab[i];
-        for (int i = threadIdx.x; i < kTransEntries; i += kWordsThreads) s_transd[i] = g_transd[i];
+        for (int i = threadIdx.x; i < kDevTabEntries; i += blockDim.x) s_tab[i] = g_tab[i];
+        for (int i = threadIdx.x; i < kTransEntries; i += blockDim.x) s_transd[i] = g_transd[i];
     }
     __syncthreads();
     unsigned *counter = (unsigned *)(a.scratch[0] + kScrBarrier), *err = (unsigned *)(scr + kScrErr);
     const uint32_t b = blockIdx.x - a.first_block[li], nb = a.first_block[li + 1] - a.first_block[li];
     const uint32_t my_sweeps = a.sweeps[li];
     const uint32_t csz = (uint32_t)(d.L >> 1) * (uint32_t)(d.L >> 6);
-    const uint32_t n_tasks = (uint32_t)Q * csz, stride = nb * kWordsThreads;
-    const uint32_t first = b * kWordsThreads + threadIdx.x;
+    const uint32_t n_tasks = (uint32_t)Q * csz, stride = nb * blockDim.x;
+    const uint32_t first = b * blockDim.x + threadIdx.x;
+    // At most one task a thread (uniform per lattice): its Philox draws for
+    // the next phase are made while the block waits at the barrier, where
+    // they depend on nothing the other blocks write.
+    const bool one = stride >= n_tasks, mine = one && first < n_tasks;
+    const int q = (int)(first & (uint32_t)(Q - 1));
+    u32x4 pre[kTaskCalls<Q>];
+    uint32_t c0 = 0;
+    auto draws = [&](uint64_t s, int p) {
+#pragma unroll
+        for (int i = 0; i < kTaskCalls<Q>; ++i)
+            pre[i] = philox4x32_10((uint32_t)s, (uint32_t)p, c0 + (uint32_t)call_of_task<Q>(q, i), (uint32_t)(s >> 32),
+                                   d.key0, d.key1);
+    };
+    int r, mm[4], kk[4];
+    device_schedule(d.L, d.key0, d.key1, d.next_sweep, r, mm, kk);
+    if (mine && my_sweeps > 0) {
+        WordPhase f0;
+        word_phase_setup(f0, d.L, d.key0, d.key1, d.next_sweep, 0, r, mm, kk);
+        c0 = task_call0<Q>(f0, first);
+        draws(d.next_sweep, 0);
+    }
     int tr[3] = {0, 0, 0};
     int dv[3] = {0, 0, 0};  // Obs: spin, staggered spin, staggered charge moves
     unsigned arrivals = 0;
@@ -127,15 +147,20 @@ __global__ void __launch_bounds__(kWordsThreads) k_words_series(WordsSeriesArgs 
         for (uint32_t e = 0; e < a.every; ++e) {
             const uint32_t it = k * a.every + e;
             const uint64_t s = d.next_sweep + it;
-            int r, mm[4], kk[4];
-            device_schedule(d.L, d.key0, d.key1, s, r, mm, kk);
             for (int p = 0; p < 4; ++p) {
                 if (it < my_sweeps) {
                     WordPhase f;
                     word_phase_setup(f, d.L, d.key0, d.key1, s, p, r, mm, kk);
-                    // stride is a multiple of Q: a word's lanes are all in or all out
-                    for (uint32_t t = first; t < n_tasks; t += stride)
-                        word_task<Q, false, false, true, true, Obs>(st, f, t, s_tab, s_transd, tr, nullptr, 0, 0, dv);
+                    if (one) {
+                        if (mine)
+                            word_task<Q, false, kDrawGiven, true, true, Obs>(st, f, first, s_tab, s_transd, tr, pre, 0,
+                                                                             0, dv);
+                    } else {
+                        // stride is a multiple of Q: a word's lanes are all in or all out
+                        for (uint32_t t = first; t < n_tasks; t += stride)
+                            word_task<Q, false, kDrawInPlace, true, true, Obs>(st, f, t, s_tab, s_transd, tr, nullptr,
+                                                                               0, 0, dv);
+                    }
                 }
                 if constexpr (Obs) {
                     if (p == 3 && e + 1 == a.every) {
@@ -148,7 +173,13 @@ __global__ void __launch_bounds__(kWordsThreads) k_words_series(WordsSeriesArgs 
                     }
                 }
                 arrivals += gridDim.x;
-                grid_barrier_coherent(counter, arrivals, err);
+                grid_arrive_coherent(counter);
+                // the next phase's schedule and draws, while the others arrive
+                const uint32_t it_next = p < 3 ? it : it + 1;
+                const uint64_t s_next = p < 3 ? s : s + 1;
+                if (p == 3) device_schedule(d.L, d.key0, d.key1, s_next, r, mm, kk);
+                if (mine && it_next < my_sweeps) draws(s_next, p < 3 ? p + 1 : 0);
+                grid_wait_coherent(counter, arrivals, err);
             }
         }
     }
@@ -293,7 +324,7 @@ const void *series_fn_of(int Q, bool obs)
 }
 }  // namespace
 
-int words_persistent_capacity(int Q)
+int words_persistent_capacity(int Q, int threads)
 {
     int dev = 0, coop = 0, per_cu = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -302,7 +333,7 @@ int words_persistent_capacity(int Q)
     // the smaller of the two forms' (with and without records) resident blocks
     for (const bool obs : {false, true}) {
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, series_fn_of(Q, obs), kWordsThreads, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, series_fn_of(Q, obs), threads, 0) != hipSuccess ||
             n < 1)
             return 0;
         per_cu = obs ? std::min(per_cu, n) : n;
@@ -324,7 +355,7 @@ hipError_t launch_words_series(const WordsSeriesArgs &a, int Q, hipStream_t s)
     WordsSeriesArgs args = a;
     void *kargs[] = {&args};
     return hipLaunchCooperativeKernel(series_fn_of(Q, a.records != nullptr), dim3(a.first_block[a.count]),
-                                      dim3(kWordsThreads), kargs, 0, s);
+                                      dim3((unsigned)a.threads), kargs, 0, s);
 }
 
 hipError_t launch_advance_words(const WordsArgs &a, hipStream_t s)

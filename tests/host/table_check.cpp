@@ -20,7 +20,7 @@ hipError_t launch_observables(uint8_t *, const void *, int, int, hipStream_t, lo
 int words_lanes(int) { return 1; }
 hipError_t launch_phase_words(const WordsArgs &, int, int, hipStream_t) { return hipSuccess; }
 hipError_t launch_advance_words(const WordsArgs &, hipStream_t) { return hipSuccess; }
-int words_persistent_capacity(int) { return 0; }
+int words_persistent_capacity(int, int) { return 0; }
 hipError_t launch_words_series(const WordsSeriesArgs &, int, hipStream_t) { return hipSuccess; }
 hipError_t launch_pack_int8(const int8_t *, uint32_t *, int, hipStream_t) { return hipSuccess; }
 hipError_t launch_unpack_int8(const uint32_t *, int8_t *, int, hipStream_t) { return hipSuccess; }

@@ -255,6 +255,35 @@ def test_mixed_paths_in_one_batch_match_oracle(persistent, monkeypatch):
             assert [go.track_nD, go.track_nV, go.track_nJ] == o.track.tolist()
 
 
+@pytest.mark.parametrize("block", ["64", "128"])
+def test_persistent_word_kernel_small_blocks_match_oracle(block, monkeypatch):
+    """The persistent word kernel in blocks of 64 or 128 threads: the mid
+    lattice's observation series (records from the tracked moves), and one
+    call for four L = 2048 lattices that share the resident blocks, so that a
+    thread holds two word tasks a phase (draws made in place) -- bit-exact
+    against the oracle."""
+    monkeypatch.setenv("LATTICE_WORDS_PERSISTENT", "1")
+    monkeypatch.setenv("LATTICE_WORDS_SERIES_BLOCK", block)
+    _say(f"case persistent series block={block} L=1024")
+    g, o = _pair(workloads.MID)
+    recs = g.sweep_series(5, 1)
+    for k, r in enumerate(recs):
+        o.sweeps(1)
+        assert r.ints() == o.observables().tolist(), k
+        assert [r.track_nD, r.track_nV, r.track_nJ] == o.track.tolist(), k
+    _assert_same(g, o, "after the series")
+    g.destroy()
+    _say(f"case persistent batch block={block} 4 x L=2048")
+    specs = [SMALL.with_(L=2048, encoding=1, seed=1600 + i, T=0.8 + 0.3 * i) for i in range(4)]
+    gs = [_make(s) for s in specs]
+    os_ = [_oracle(s) for s in specs]
+    lat.sweep_batch(gs, 2)
+    for s, g, o in zip(specs, gs, os_):
+        o.sweeps(2)
+        _assert_same(g, o, f"L={s.L} seed={s.seed}")
+        g.destroy()
+
+
 @pytest.mark.parametrize("rows,bpc", [(1, 1), (2, 4), (32, 1), (8, 2)])
 def test_phase_kernel_launch_shapes_match_oracle(rows, bpc, monkeypatch):
     """The 2-bit phase kernel under other launch shapes (rows of the a-class
