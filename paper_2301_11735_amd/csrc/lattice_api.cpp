@@ -621,14 +621,15 @@ namespace {
 struct TuneEntry {
     std::vector<int> candidates;
     std::vector<double> ns_per_update;  // < 0: not measured yet
-    int pending = -1;                   // candidate being timed by the current launch
-    hipEvent_t start = nullptr, stop = nullptr;
+    std::vector<double> in_flight;      // > 0: site updates of a timed launch not yet read
+    std::vector<hipEvent_t> start, stop;
     int best = -1;
 };
 
+using TuneKey = std::pair<int, int>;  // (max L | word form << 20, batch size rounded up to a power of 2)
 std::mutex g_tune_mu;
-std::map<std::pair<int, int>, TuneEntry> g_tune;
-std::vector<std::pair<int, int>> g_tune_slots;
+std::map<TuneKey, TuneEntry> g_tune;
+std::vector<std::pair<TuneKey, int>> g_tune_slots;  // (shape, candidate) of each timed launch handed out
 
 int pinned_batch_threads()
 {
@@ -636,11 +637,48 @@ int pinned_batch_threads()
     return v ? std::atoi(v) : 0;
 }
 
+TuneKey tune_key(int max_L, int count, bool word)
+{
+    int bucket = 1;
+    while (bucket < count) bucket *= 2;
+    return std::make_pair(max_L | (word ? 1 << 20 : 0), bucket);
+}
+
+// Reads the timed launches of a shape that have completed (never waits), and
+// picks the fastest candidate once all are measured.  Caller holds g_tune_mu.
+void harvest(TuneEntry &t)
+{
+    bool all = true;
+    for (size_t i = 0; i < t.candidates.size(); ++i) {
+        if (t.in_flight[i] > 0) {
+            const hipError_t q = hipEventQuery(t.stop[i]);
+            if (q == hipErrorNotReady) {
+                all = false;
+                continue;
+            }
+            float ms = 0.f;
+            if (q == hipSuccess && hipEventElapsedTime(&ms, t.start[i], t.stop[i]) == hipSuccess)
+                t.ns_per_update[i] = (double)ms * 1e6 / t.in_flight[i];
+            else
+                t.ns_per_update[i] = 1e30;  // not usable: ranks last
+            t.in_flight[i] = 0;
+        }
+        all = all && t.ns_per_update[i] >= 0;
+    }
+    if (all && t.best < 0) {
+        t.best = 0;
+        for (size_t i = 1; i < t.ns_per_update.size(); ++i)
+            if (t.ns_per_update[i] < t.ns_per_update[(size_t)t.best]) t.best = (int)i;
+    }
+}
+
 }  // namespace
 
-// Returns the block size to use (0 = default) and, while tuning, events to
-// record around the launch plus a slot for batch_threads_done, which waits
-// for that launch (the first calls for a new shape are therefore blocking).
+// Returns the block size to use (0 = default) and, while the shape is being
+// tuned, events to record around the launch plus a slot for
+// batch_threads_done.  No call waits: each of the first calls for a new
+// shape times one candidate that has not been timed yet, and the timings
+// are read by later calls once their launches have completed.
 int batch_threads_for(int max_L, int count, bool word, hipStream_t stream, hipEvent_t *start, hipEvent_t *stop,
                       int *slot)
 {
@@ -648,10 +686,8 @@ int batch_threads_for(int max_L, int count, bool word, hipStream_t stream, hipEv
     *start = *stop = nullptr;
     *slot = -1;
     if (const int pinned = pinned_batch_threads()) return pinned;
-    int bucket = 1;
-    while (bucket < count) bucket *= 2;
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    const auto key = std::make_pair(max_L | (word ? 1 << 20 : 0), bucket);
+    const TuneKey key = tune_key(max_L, count, word);
     TuneEntry &t = g_tune[key];
     if (t.candidates.empty()) {
         if (word) {
@@ -664,54 +700,57 @@ int batch_threads_for(int max_L, int count, bool word, hipStream_t stream, hipEv
             for (int c : {1024, 512, 256})
                 if (c / 2 < calls || c == 256) t.candidates.push_back(c);
         }
-        t.ns_per_update.assign(t.candidates.size(), -1.0);
+        const size_t n = t.candidates.size();
+        t.ns_per_update.assign(n, -1.0);
+        t.in_flight.assign(n, 0.0);
+        t.start.assign(n, nullptr);
+        t.stop.assign(n, nullptr);
     }
-    if (t.best >= 0) return t.candidates[t.best];
+    harvest(t);
+    if (t.best >= 0) return t.candidates[(size_t)t.best];
     for (size_t i = 0; i < t.candidates.size(); ++i) {
-        if (t.ns_per_update[i] < 0) {
-            if (!t.start) {
-                if (hipEventCreate(&t.start) != hipSuccess || hipEventCreate(&t.stop) != hipSuccess) return 0;
+        if (t.ns_per_update[i] < 0 && t.in_flight[i] <= 0) {
+            if (!t.start[i]) {
+                if (hipEventCreate(&t.start[i]) != hipSuccess) return 0;
+                if (hipEventCreate(&t.stop[i]) != hipSuccess) {
+                    (void)hipEventDestroy(t.start[i]);
+                    t.start[i] = nullptr;
+                    return 0;
+                }
             }
-            t.pending = (int)i;
-            *start = t.start;
-            *stop = t.stop;
-            g_tune_slots.push_back(key);
-            *slot = (int)g_tune_slots.size() - 1;
+            *start = t.start[i];
+            *stop = t.stop[i];
+            const auto entry = std::make_pair(key, (int)i);
+            auto it = std::find(g_tune_slots.begin(), g_tune_slots.end(), entry);
+            if (it == g_tune_slots.end()) it = g_tune_slots.insert(g_tune_slots.end(), entry);
+            *slot = (int)(it - g_tune_slots.begin());
             return t.candidates[i];
         }
     }
-    return 0;
+    return 0;  // every untimed candidate has a launch in flight: the default meanwhile
 }
 
+// The launch timed for `slot` has been enqueued between its events with
+// `site_updates` site updates; its time is read by a later call.
 void batch_threads_done(int slot, double site_updates)
 {
     if (slot < 0) return;
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    TuneEntry &t = g_tune[g_tune_slots[(size_t)slot]];
-    if (t.pending < 0) return;
-    float ms = 0.f;
-    if (hipEventSynchronize(t.stop) != hipSuccess || hipEventElapsedTime(&ms, t.start, t.stop) != hipSuccess) return;
-    t.ns_per_update[t.pending] = site_updates > 0 ? (double)ms * 1e6 / site_updates : 0.0;
-    t.pending = -1;
-    bool all = true;
-    for (double v : t.ns_per_update) all = all && v >= 0;
-    if (all) {
-        t.best = 0;
-        for (size_t i = 1; i < t.ns_per_update.size(); ++i)
-            if (t.ns_per_update[i] < t.ns_per_update[(size_t)t.best]) t.best = (int)i;
-    }
+    const auto &entry = g_tune_slots[(size_t)slot];
+    TuneEntry &t = g_tune[entry.first];
+    t.in_flight[(size_t)entry.second] = site_updates > 0 ? site_updates : 1.0;
 }
 
-// The tuned block size for a batch shape if tuning has finished, else 0
-// (the default); never launches anything.
+// The tuned block size for a batch shape if tuning has finished (reading
+// completed timings first), else 0 (the default); never launches anything.
 int batch_threads_tuned(int max_L, int count, bool word)
 {
     if (const int pinned = pinned_batch_threads()) return pinned;
-    int bucket = 1;
-    while (bucket < count) bucket *= 2;
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    const auto it = g_tune.find(std::make_pair(max_L | (word ? 1 << 20 : 0), bucket));
-    return it != g_tune.end() && it->second.best >= 0 ? it->second.candidates[(size_t)it->second.best] : 0;
+    const auto it = g_tune.find(tune_key(max_L, count, word));
+    if (it == g_tune.end()) return 0;
+    harvest(it->second);
+    return it->second.best >= 0 ? it->second.candidates[(size_t)it->second.best] : 0;
 }
 
 int enqueue_observables_batch(lattice *const *hs, int32_t count, unsigned long long *dev, hipStream_t stream)

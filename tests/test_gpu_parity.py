@@ -449,8 +449,8 @@ def test_persistent_path_matches_oracle(spec, monkeypatch):
 
 def test_autotuned_batch_launch_shapes_match_oracle():
     """The first calls for a new batch shape each try another block size
-    (1024, 512, 256 threads per lattice) before the fastest is kept; every
-    call must leave every lattice bit-exact."""
+    (1024, 512, 256, 128 threads per lattice) before the fastest is kept;
+    every call must leave every lattice bit-exact."""
     _say("case autotuned batch shapes")
     specs = [SMALL.with_(L=L, encoding=1, seed=900 + i, T=0.4 + 0.2 * i) for i, L in enumerate([192, 192, 128, 64, 192])]
     gs = [_make(s) for s in specs]
@@ -460,6 +460,19 @@ def test_autotuned_batch_launch_shapes_match_oracle():
         for s, g, o in zip(specs, gs, os_):
             o.sweeps(k)
             assert np.array_equal(g.read_state(), o.codes), f"call {call} L={s.L}"
+    # A new shape (three lattices) called back to back with no read between:
+    # the timed launches of several candidates are in flight at once, and no
+    # call waits for them.
+    _say("case autotuned batch shapes, calls back to back")
+    specs = [SMALL.with_(L=128, encoding=1, seed=950 + i, T=0.5 + 0.4 * i) for i in range(3)]
+    gs = [_make(s) for s in specs]
+    os_ = [_oracle(s) for s in specs]
+    ks = [2, 3, 1, 2, 3, 2, 1]
+    for k in ks:
+        lat.sweep_batch(gs, k)
+    for s, g, o in zip(specs, gs, os_):
+        o.sweeps(sum(ks))
+        assert np.array_equal(g.read_state(), o.codes), f"L={s.L} seed={s.seed}"
 
 
 def _word_batch_specs():
