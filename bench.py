@@ -468,12 +468,22 @@ def served_run(seconds: float) -> dict:
     done, wall, st = serve_mod.serve(reqs, 8 << 20, 256, 1 << 22, progress=False)
     lats = [d["latency"] for d in done.values()]
     updates = sum(d["L"] ** 2 * d["sweeps"] for d in done.values())
+
+    def pct(v, q):
+        v = sorted(v)
+        return float(v[min(len(v) - 1, int(q * len(v)))]) if v else None
+
+    by_L = {}
+    for L in sorted({d["L"] for d in done.values()}):
+        v = [d["latency"] for d in done.values() if d["L"] == L]
+        by_L[str(L)] = {"requests": len(v), "p50_s": pct(v, 0.5), "p99_s": pct(v, 0.99)}
     return {
         "workload": f"Poisson 200 req/s for {seconds:g} s, L in {{64,128,256,512}}, 500-5000 sweeps, 8 MiB pool, 256 slots",
         "requests": len(reqs),
         "completed": len(done),
-        "p50_s": float(sorted(lats)[len(lats) // 2]) if lats else None,
-        "p99_s": float(sorted(lats)[min(len(lats) - 1, int(0.99 * len(lats)))]) if lats else None,
+        "p50_s": pct(lats, 0.5),
+        "p99_s": pct(lats, 0.99),
+        "by_L": by_L,
         "site_updates_per_s": updates / wall,
     }
 
