@@ -621,7 +621,8 @@ namespace {
 struct TuneEntry {
     std::vector<int> candidates;
     std::vector<double> ns_per_update;  // < 0: not measured yet
-    std::vector<double> in_flight;      // > 0: site updates of a timed launch not yet read
+    std::vector<double> in_flight;      // > 0: site updates of a timed launch not yet read;
+                                        // < 0: handed out, not yet enqueued
     std::vector<hipEvent_t> start, stop;
     int best = -1;
 };
@@ -709,7 +710,7 @@ int batch_threads_for(int max_L, int count, bool word, hipStream_t stream, hipEv
     harvest(t);
     if (t.best >= 0) return t.candidates[(size_t)t.best];
     for (size_t i = 0; i < t.candidates.size(); ++i) {
-        if (t.ns_per_update[i] < 0 && t.in_flight[i] <= 0) {
+        if (t.ns_per_update[i] < 0 && t.in_flight[i] == 0) {
             if (!t.start[i]) {
                 if (hipEventCreate(&t.start[i]) != hipSuccess) return 0;
                 if (hipEventCreate(&t.stop[i]) != hipSuccess) {
@@ -720,6 +721,7 @@ int batch_threads_for(int max_L, int count, bool word, hipStream_t stream, hipEv
             }
             *start = t.start[i];
             *stop = t.stop[i];
+            t.in_flight[i] = -1.0;  // no other call takes these events meanwhile
             const auto entry = std::make_pair(key, (int)i);
             auto it = std::find(g_tune_slots.begin(), g_tune_slots.end(), entry);
             if (it == g_tune_slots.end()) it = g_tune_slots.insert(g_tune_slots.end(), entry);
