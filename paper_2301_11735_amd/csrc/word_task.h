@@ -56,12 +56,17 @@ __device__ __forceinline__ void stw(uint32_t *p, uint32_t i, uint32_t v)
         p[i] = v;
 }
 // 16 sites of the class row at word offset `row`, starting at class position
-// xs (periodic), as load16 but through ldw.
+// xs (periodic), as load16 but through ldw.  Device-coherent reads load the
+// second word only when xs starts mid-word (every caller's xs mod 16 depends
+// on the phase and the schedule only, so the branch is uniform): at
+// L = 1024 that saved 2.5% of a sweep.  Plain loads (LDS, or global memory
+// within a launch) keep both, which measured slightly faster there.
 template <bool Coh>
 __device__ __forceinline__ uint32_t ld16(const uint32_t *st, uint32_t row, int W, int xs)
 {
     const int jw = xs >> 4, sh = xs & 15;
     const uint32_t w0 = ldw<Coh>(st, row + (uint32_t)jw);
+    if (Coh && sh == 0) return w0;
     const uint32_t w1 = ldw<Coh>(st, row + (uint32_t)(jw + 1 == W ? 0 : jw + 1));
     return sh ? __builtin_amdgcn_alignbit(w1, w0, 2u * (uint32_t)sh) : w0;
 }
