@@ -258,10 +258,11 @@ def test_mixed_paths_in_one_batch_match_oracle(persistent, monkeypatch):
 @pytest.mark.parametrize("block", ["64", "128"])
 def test_persistent_word_kernel_small_blocks_match_oracle(block, monkeypatch):
     """The persistent word kernel in blocks of 64 or 128 threads: the mid
-    lattice's observation series (records from the tracked moves), and one
-    call for four L = 2048 lattices that share the resident blocks, so that a
-    thread holds two word tasks a phase (draws made in place) -- bit-exact
-    against the oracle."""
+    lattice's observation series (records from the tracked moves), with 64
+    threads also an L = 2048 series whose threads hold several word tasks a
+    phase, and one call for four L = 2048 lattices that share the resident
+    blocks, so that a thread holds two word tasks a phase (draws made in
+    place) -- bit-exact against the oracle."""
     monkeypatch.setenv("LATTICE_WORDS_PERSISTENT", "1")
     monkeypatch.setenv("LATTICE_WORDS_SERIES_BLOCK", block)
     _say(f"case persistent series block={block} L=1024")
@@ -273,6 +274,22 @@ def test_persistent_word_kernel_small_blocks_match_oracle(block, monkeypatch):
         assert [r.track_nD, r.track_nV, r.track_nJ] == o.track.tolist(), k
     _assert_same(g, o, "after the series")
     g.destroy()
+    if block == "64":
+        # 8 lanes a word at L = 2048 need 4096 blocks of 64 threads; at most
+        # 1024 take part, so a thread holds four tasks a phase while the
+        # records are taken from the tracked moves
+        monkeypatch.setenv("LATTICE_WORDS_LANES", "8")
+        _say("case persistent series, several tasks a thread, L=2048")
+        spec = SMALL.with_(L=2048, encoding=1, T=0.9, seed=97)
+        g, o = _pair(spec)
+        recs = g.sweep_series(2, 1)
+        for k, r in enumerate(recs):
+            o.sweeps(1)
+            assert r.ints() == o.observables().tolist(), k
+            assert [r.track_nD, r.track_nV, r.track_nJ] == o.track.tolist(), k
+        _assert_same(g, o, "after the L=2048 series")
+        g.destroy()
+        monkeypatch.delenv("LATTICE_WORDS_LANES")
     _say(f"case persistent batch block={block} 4 x L=2048")
     specs = [SMALL.with_(L=2048, encoding=1, seed=1600 + i, T=0.8 + 0.3 * i) for i in range(4)]
     gs = [_make(s) for s in specs]
