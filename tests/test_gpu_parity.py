@@ -545,18 +545,24 @@ def test_word_and_site_batch_forms_agree(monkeypatch):
         assert oa.as_dict() == ob.as_dict()
 
 
-@pytest.mark.parametrize("kind,threads", [("word", 0), ("word", 512), ("word", 1024), ("site", 0)],
-                         ids=["word-auto", "word-512", "word-1024", "site"])
+@pytest.mark.parametrize("kind,threads", [("word", 0), ("word", 512), ("word", 1024), ("site", 0),
+                                          ("onchip", 0), ("onchip", 512)],
+                         ids=["word-auto", "word-512", "word-1024", "site", "onchip-auto", "onchip-512"])
 def test_batch_graph_replays_match_eager_and_oracle(kind, threads, monkeypatch):
     """Observation intervals captured into a HIP graph: every replay (with
     eager batched work and synchronisation in between) leaves the lattices and
     every interval's observables exactly where the same eager calls do, and
     where the oracle does.  512-thread word blocks reduce the observables in
-    the sweep kernel, 1024-thread ones in a separate launch: both covered."""
+    the sweep kernel, 1024-thread ones in a separate launch: both covered,
+    also for a batch whose lattices are all on the on-chip path (onchip-512;
+    onchip-auto takes 1024 threads at L = 256)."""
     if threads:
         monkeypatch.setenv("LATTICE_BATCH_THREADS", str(threads))
     _say(f"case batch graph {kind} threads={threads}")
-    if kind == "word":
+    if kind == "onchip":
+        specs = [SMALL.with_(L=L, encoding=enc, seed=1450 + i, T=0.4 + 0.35 * i)
+                 for i, (L, enc) in enumerate([(64, 0), (64, 1), (128, 1), (192, 1), (256, 0)])]
+    elif kind == "word":
         specs = _word_batch_specs()
     else:
         specs = [SMALL.with_(L=L, encoding=enc, seed=1400 + i, T=0.3 + 0.4 * i)
