@@ -196,12 +196,14 @@ int lattice_observables_batch_noalloc(lattice *const *hs, int32_t count, lat_obs
  * observables into its own slot of the device buffer d_out (slot k at byte
  * 80*count*k, 80 bytes per lattice, as lattice_observables_batch), so a whole
  * observable series is produced with one graph launch and read with one copy.
- * Every lattice must take the on-chip batched path (L <= 512).  The capture
- * runs on a private stream and launches nothing; replays run on hip_stream,
- * which the caller orders after the lattices' other work.  The lattices and
- * d_out must outlive the graph.
+ * Every lattice must take the on-chip batched path (L <= 256 with
+ * L % 64 == 0, L <= 512 otherwise) or the multi-block word path (L % 64 == 0
+ * up to 2048, one launch per phase in the graph).  The capture runs on a
+ * private stream and launches nothing; replays run on hip_stream, which the
+ * caller orders after the lattices' other work.  The lattices and d_out must
+ * outlive the graph.
  * Errors: LAT_EINVAL (empty or duplicate batch, sweeps == 0, intervals == 0,
- * a lattice with L > 512, null pointers), LAT_ENOMEM (d_out smaller than
+ * a lattice on neither path, null pointers), LAT_ENOMEM (d_out smaller than
  * 80*count*intervals bytes), LAT_ESTATE, LAT_EHIP. */
 typedef struct lat_batch_graph lat_batch_graph;
 int lattice_batch_graph_create(lattice *const *hs, int32_t count, uint32_t sweeps, uint32_t intervals, void *d_out,

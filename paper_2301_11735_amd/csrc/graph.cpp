@@ -97,9 +97,14 @@ int lattice_batch_graph_create(lattice *const *hs, int32_t count, uint32_t sweep
                     rc = enqueue_lds_sweeps(g->hs.data(), count, nullptr, sweeps, cs, /*tune=*/false, slot);
                 } else {
                     // the multi-block word path computes its schedules on the
-                    // device, so its launch series replays like the on-chip one
+                    // device, so its launch series replays like the on-chip
+                    // one; one launch per phase, since a graph's kernel node
+                    // does not guarantee the co-residency that the persistent
+                    // form's device-wide barrier needs
                     rc = enqueue_lds_sweeps(small.data(), (int32_t)small.size(), nullptr, sweeps, cs, false);
-                    if (rc == LAT_OK) rc = enqueue_offchip_sweeps(big.data(), (int32_t)big.size(), nullptr, sweeps, cs);
+                    if (rc == LAT_OK)
+                        rc = enqueue_offchip_sweeps(big.data(), (int32_t)big.size(), nullptr, sweeps, cs,
+                                                    /*convert=*/true, /*persistent=*/false);
                     if (rc == LAT_OK) rc = enqueue_observables_batch(g->hs.data(), count, slot, cs);
                 }
             }
