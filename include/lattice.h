@@ -124,7 +124,9 @@ int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void 
  * 0.2 s marks the state invalid, which the next read (lattice_observables,
  * lattice_observables_batch, lattice_series_read) reports as LAT_EHIP.
  * LATTICE_WORDS_PERSISTENT=0 in the environment at the call selects one
- * launch per phase instead.  Errors: LAT_ESTATE, LAT_EHIP. */
+ * launch per phase instead; set it for calls captured into a HIP graph,
+ * whose kernel nodes do not guarantee that all blocks are resident at once.
+ * Errors: LAT_ESTATE, LAT_EHIP. */
 int lattice_sweep(lattice *h, uint32_t sweeps);
 
 /* Reduce the current configuration to its integer observables, read the
