@@ -276,8 +276,6 @@ class Lattice:
     def mu_sweeps(self, first_sweep: int, n_sweeps: int, kappa: float, mu: float):
         """Penalty-mode sweeps (the prior method of section 2.2).  Returns (next mu,
         mu of each sweep, sum S after each sweep)."""
-        import numpy as np
-
         m = ctypes.c_double(mu)
         mus = np.zeros(n_sweeps, dtype=np.float64)
         sums = np.zeros(n_sweeps, dtype=np.int64)
@@ -301,9 +299,14 @@ class Lattice:
         _check(lib().lattice_sweep_series(self.handle, intervals, every, buf.data_ptr(), buf.numel()))
         return self.read_series(buf, intervals) if read else buf
 
-    def read_series(self, buf, intervals: int) -> list:
+    def read_series(self, buf, intervals: int, as_array: bool = False):
+        """The records of a device series as a list of LatObs, or (as_array)
+        as a numpy structured array over the same memory (no per-record
+        Python objects)."""
         out = (LatObs * max(1, intervals))()
         _check(lib().lattice_series_read(self.handle, buf.data_ptr(), intervals, out))
+        if as_array:
+            return np.frombuffer(out, dtype=_obs_dtype(), count=intervals)
         return list(out)[:intervals]
 
     def observables(self) -> LatObs:
@@ -344,6 +347,18 @@ def sweep_batch(lattices, sweeps: int, stream=None):
     _check(lib().lattice_sweep_batch(_handles(lattices), len(lattices), sweeps, _stream_handle(stream)))
 
 
+_OBS_DTYPE = None
+
+
+def _obs_dtype():
+    """numpy dtype of LatObs, built once (record arrays are views of the
+    library's output with it)."""
+    global _OBS_DTYPE
+    if _OBS_DTYPE is None:
+        _OBS_DTYPE = np.dtype(LatObs)
+    return _OBS_DTYPE
+
+
 class BatchObservables:
     """Reusable device output buffer for observables_batch()."""
 
@@ -353,14 +368,24 @@ class BatchObservables:
         self.capacity = capacity
         self.buf = torch.empty(80 * max(1, capacity), dtype=torch.uint8, device=device)
 
-    def __call__(self, lattices, stream=None) -> list:
+    def _read(self, lattices, stream):
         n = len(lattices)
         if n > self.capacity:
             raise ValueError("more lattices than the buffer holds")
         out = (LatObs * max(1, n))()
         _check(lib().lattice_observables_batch(_handles(lattices), n, self.buf.data_ptr(), self.buf.numel(), out,
                                                _stream_handle(stream)))
+        return out, n
+
+    def __call__(self, lattices, stream=None) -> list:
+        out, n = self._read(lattices, stream)
         return list(out)[:n]
+
+    def array(self, lattices, stream=None):
+        """The same records as a numpy structured array (no per-record
+        Python objects)."""
+        out, n = self._read(lattices, stream)
+        return np.frombuffer(out, dtype=_obs_dtype(), count=n)
 
 
 def observables_batch_noalloc(lattices, stream=None) -> list:
@@ -402,12 +427,10 @@ class BatchGraph:
 
     def read_array(self):
         """The same records as a numpy structured array of shape (intervals, lattices)."""
-        import numpy as np
-
         n = len(self._lats)
         out = (LatObs * (n * self.intervals))()
         _check(lib().lattice_batch_graph_read(self._h, out))
-        return np.ctypeslib.as_array(out).reshape(self.intervals, n)
+        return np.frombuffer(out, dtype=_obs_dtype(), count=n * self.intervals).reshape(self.intervals, n)
 
     def destroy(self):
         if self._h:
