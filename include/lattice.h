@@ -121,7 +121,8 @@ int lattice_create(const lat_params *p, void *d_state, size_t state_bytes, void 
  * launch per call, whose blocks must all be resident at once, with a
  * device-wide barrier after every phase: kernels of other streams running
  * at the same time can delay it, and a barrier that waits longer than about
- * 0.2 s marks the state invalid, which the next read (lattice_observables,
+ * 0.2 s (LATTICE_BARRIER_TICKS: another bound, in 10 ns ticks of the device
+ * clock) marks the state invalid, which the next read (lattice_observables,
  * lattice_observables_batch, lattice_series_read) reports as LAT_EHIP.
  * LATTICE_WORDS_PERSISTENT=0 in the environment at the call selects one
  * launch per phase instead; set it for calls captured into a HIP graph,

@@ -235,7 +235,6 @@ __device__ __forceinline__ void device_schedule(int L, uint32_t k0, uint32_t k1,
 // constant-rate wall clock, 0.2 s at its 100 MHz): then the block raises the
 // error flag and goes on (results are then invalid and reported as an
 // error), so no wave can spin for long.
-constexpr long long kBarrierTimeoutTicks = 20000000;
 __device__ __forceinline__ void grid_barrier(unsigned *counter, unsigned target, unsigned *err)
 {
     __threadfence();

@@ -116,6 +116,10 @@ struct PhaseArgs {
 // W < 2^22.
 inline uint32_t magic_div(uint32_t W) { return W <= 1 ? 0u : (uint32_t)((0x100000000ull + W - 1u) / W); }
 
+// Bound of a device-wide barrier wait in the persistent kernels: ticks of
+// the device's constant-rate wall clock (100 MHz), 0.2 s.
+constexpr long long kBarrierTimeoutTicks = 20000000;
+
 // One phase of up to kWordsBatch lattices in the 2-bit class layout (int8
 // ones through their packed copy), spread over many blocks per lattice:
 // blocks first_block[i] .. first_block[i+1]-1 update lattice i, Q lanes per
@@ -156,7 +160,8 @@ hipError_t launch_advance_words(const WordsArgs &a, hipStream_t s);
 // kernels enqueued first.
 struct WordsSeriesArgs {
     int count;
-    int threads;  // block size: a multiple of 64 up to kWordsThreads
+    int threads;              // block size: a multiple of 64 up to kWordsThreads
+    long long barrier_ticks;  // bound of each device-wide barrier wait (device wall-clock ticks)
     uint32_t intervals, every;
     long long *records;  // null: no observables
     uint8_t *scratch[kWordsBatch];

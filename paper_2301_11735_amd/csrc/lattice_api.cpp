@@ -453,6 +453,20 @@ int words_capacity(int Q, int threads)
     return it->second;
 }
 
+// Bound of each device-wide barrier wait of the persistent word kernel:
+// kBarrierTimeoutTicks unless LATTICE_BARRIER_TICKS asks for another
+// (non-negative) count; tests use a tiny one to force the time-out path,
+// whose kernels still end normally (a wait that times out flags the state
+// invalid and goes on).
+long long words_barrier_ticks()
+{
+    if (const char *v = std::getenv("LATTICE_BARRIER_TICKS")) {
+        const long long want = std::atoll(v);
+        if (want >= 0) return want;
+    }
+    return kBarrierTimeoutTicks;
+}
+
 // Block size of the persistent word kernel: 256 threads unless
 // LATTICE_WORDS_SERIES_BLOCK asks for another multiple of 64 up to 256
 // (smaller blocks spread a lattice over more compute units).
@@ -530,6 +544,7 @@ int enqueue_words_persistent(lattice *const *hs, int32_t count, const uint32_t *
                 WordsSeriesArgs a{};
                 a.count = 1;
                 a.threads = threads;
+                a.barrier_ticks = words_barrier_ticks();
                 a.intervals = std::min(intervals_cap, intervals - k);
                 a.every = every;
                 a.records = records + (kSeriesRecord / 8) * (size_t)k;
@@ -550,6 +565,7 @@ int enqueue_words_persistent(lattice *const *hs, int32_t count, const uint32_t *
         for (uint32_t c = 0; c < most; c += sweeps_cap) {
             WordsSeriesArgs a{};
             a.threads = threads;
+            a.barrier_ticks = words_barrier_ticks();
             a.intervals = 1;
             a.every = 0;
             uint32_t blocks = 0;

@@ -78,20 +78,21 @@ __device__ __forceinline__ uint32_t ld16(const uint32_t *st, uint32_t row, int W
 // thread waits for the others, and the block meets again.  No cache
 // write-back or invalidation is needed.  Between the halves a block may do
 // work that touches no lattice word.  The wait is bounded as in grid_barrier
-// (time-out flag, then go on).
+// (time-out flag, then go on), by `limit` ticks of the device wall clock.
 __device__ __forceinline__ void grid_arrive_coherent(unsigned *counter)
 {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void grid_wait_coherent(unsigned *counter, unsigned target, unsigned *err)
+__device__ __forceinline__ void grid_wait_coherent(unsigned *counter, unsigned target, unsigned *err,
+                                                   long long limit = kBarrierTimeoutTicks)
 {
     if (threadIdx.x == 0) {
         const long long t0 = wall_clock64();
         while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
-            if (wall_clock64() - t0 > kBarrierTimeoutTicks) {
+            if (wall_clock64() - t0 > limit) {
                 atomicOr(err, 1u);
                 break;
             }

@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(kWordsThreads) k_words_series(WordsSeriesArgs 
                 const uint64_t s_next = p < 3 ? s : s + 1;
                 if (p == 3) device_schedule(d.L, d.key0, d.key1, s_next, r, mm, kk);
                 if (mine && it_next < my_sweeps) draws(s_next, p < 3 ? p + 1 : 0);
-                grid_wait_coherent(counter, arrivals, err);
+                grid_wait_coherent(counter, arrivals, err, a.barrier_ticks);
             }
         }
     }
