@@ -484,7 +484,7 @@ def served_run(seconds: float) -> dict:
     for L in sorted({d["L"] for d in done.values()}):
         v = [d["latency"] for d in done.values() if d["L"] == L]
         by_L[str(L)] = {"requests": len(v), "p50_s": pct(v, 0.5), "p99_s": pct(v, 0.99)}
-    return {
+    out = {
         "workload": f"Poisson 200 req/s for {seconds:g} s, L in {{64,128,256,512}}, 500-5000 sweeps, 8 MiB pool, 256 slots",
         "requests": len(reqs),
         "completed": len(done),
@@ -493,6 +493,19 @@ def served_run(seconds: float) -> dict:
         "by_L": by_L,
         "site_updates_per_s": updates / wall,
     }
+    # the same requests one at a time with plain lattices (a sample spread
+    # over the stream), and whether each result equals the served one
+    sample = [r for r in reqs[:: max(1, len(reqs) // 100)] if r.index in done][:100]
+    if sample:
+        b2b, busy = serve_mod.back_to_back(sample)
+        work = sum(r.spec.L ** 2 * r.spec.sweeps for r in sample)
+        out["back_to_back"] = {
+            "sample": f"{len(sample)} requests spread over the stream, one plain lattice at a time",
+            "site_updates_per_s": work / busy,
+            "same_results": all(b2b[r.index]["obs"] == done[r.index]["obs"] for r in sample),
+        }
+        out["served_over_back_to_back"] = out["site_updates_per_s"] / (work / busy)
+    return out
 
 
 def main():
