@@ -43,6 +43,13 @@ BYTES_PER_SITE_UPDATE_2BIT = 0.5
 # 32x32->64 multiplies and two three-input xors, all full-rate on gfx950, so
 # 40 lane-ops per call.  Reported only as a lower bound on ALU use.
 PHILOX_OPS_PER_SITE_UPDATE = 10.0
+# LDS bytes per site update in the phase kernel: per pair one 16-byte
+# transition entry and one 8-byte threshold entry (12 B per update), and the
+# b-word exchange, a 4-byte write and a 4-byte read per thread for its 32
+# updates (0.25 B).  The tables' staging (9 KB per block, about 2% more at
+# L = 8192) is left out.  Peak: 128 B per clock per CU x 256 CUs x 2.4 GHz.
+LDS_BYTES_PER_SITE_UPDATE = 12.25
+LDS_PEAK_GBS = 128 * 256 * 2.4
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_phase_2bit_L8192_traffic.txt")
@@ -614,6 +621,14 @@ def main():
             "algorithmic_bytes_per_launch": algo_bytes,
             # what binds the kernel: VALU issue (SQ_INSTS_VALU of the committed
             # counter summary over the live launch time)
+            # LDS traffic of the table gathers and the b-word exchange
+            "lds": {
+                "bytes_per_site_update": LDS_BYTES_PER_SITE_UPDATE,
+                "achieved": per_launch_updates * LDS_BYTES_PER_SITE_UPDATE / (phase_us * 1e-6) / 1e9,
+                "peak": LDS_PEAK_GBS,
+                "unit": "GB/s",
+                "frac": per_launch_updates * LDS_BYTES_PER_SITE_UPDATE / (phase_us * 1e-6) / 1e9 / LDS_PEAK_GBS,
+            },
             "valu": {
                 "issue_frac": valu_insts * 4 / (N_SIMD * phase_us * 1e-6 * CLOCK_HZ) if valu_insts else None,
                 "lane_ops_per_site_update": valu_insts * 64 / per_launch_updates if valu_insts else None,
