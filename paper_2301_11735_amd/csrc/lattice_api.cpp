@@ -402,7 +402,12 @@ int enqueue_words_sweeps(lattice *const *hs, int32_t count, const uint32_t *swee
         a.count = std::min<int32_t>(kWordsBatch, count - b);
         int max_L = 0;
         for (int i = 0; i < a.count; ++i) max_L = std::max(max_L, hs[b + i]->L);
-        const int Q = words_lanes(max_L);
+        int Q = words_lanes(max_L);
+        // LATTICE_WORDS_PHASE_LANES (1, 2, 4 or 8) overrides the lanes per a-word
+        if (const char *v = std::getenv("LATTICE_WORDS_PHASE_LANES")) {
+            const int want = std::atoi(v);
+            if (want == 1 || want == 2 || want == 4 || want == 8) Q = want;
+        }
         const int threads = words_phase_threads();
         uint32_t blocks = 0, most = 0;
         for (int i = 0; i < a.count; ++i) {

@@ -287,9 +287,13 @@ __global__ void __launch_bounds__(256) k_unpack_int8(const uint32_t *__restrict_
 
 }  // namespace
 
+// Lanes per a-word of the per-phase form.  Up to L = 1024: 4.  The form's
+// main user below that size is the server's second stream, whose launches
+// hold several lattices beside the on-chip kernel's blocks; there 4 lanes
+// beat 8 (a 60 s served run: p99 0.224 s against 0.253-0.257 s, L = 512
+// requests 0.246 against 0.277-0.280 s; 2 lanes: 0.232-0.236 s).
 int words_lanes(int L)
 {
-    if (L <= 512) return 8;
     if (L <= 1024) return 4;
     if (L <= 2048) return 2;
     return 1;
