@@ -236,8 +236,8 @@ int lattice_batch_graph_destroy(lat_batch_graph *g);
  * being its fixed per-phase cost).  The others (L = 320 .. 512, L % 64 == 0)
  * advance on a second stream of the server at its own pace, spread over many
  * compute units (one launch per phase holds all of them): a thread of the
- * server keeps up to two chunks in flight there, each of
- * max(1, quantum_updates / 100000) sweeps of every such lattice, and a step
+ * server keeps up to three chunks in flight there, each of
+ * max(1, quantum_updates / 50000) sweeps of every such lattice, and a step
  * harvests them once the chunk holding their last sweep has completed.
  * The server's calls must come from one thread at a time.  A request's result is bit-identical to
  * running it alone with lattice_create/lattice_sweep.  Served lattices need

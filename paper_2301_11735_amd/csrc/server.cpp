@@ -52,11 +52,16 @@ constexpr size_t kAlign = 256;
 constexpr uint64_t kSweepCostSites = 11000;
 // A multi-block sweep of a lattice of L = 512 takes about 22 us on MI355X
 // (four dependent phase launches), the time the on-chip kernel needs for
-// about 100,000 site updates on its compute unit.
-constexpr uint64_t kWordsSweepCostSites = 100000;
-// Chunks of the second stream in flight at once: the next one is queued
-// while the previous runs, so that stream never waits for the host.
-constexpr int kSideChunks = 2;
+// about 100,000 site updates on its compute unit.  Chunks are sized as if it
+// cost half that (twice the sweeps, about 83 a chunk at the default
+// quantum), and three are kept in flight: the second stream then depends
+// less on how promptly its thread is scheduled.  In alternating 60 s served
+// runs this gave a p99 of 0.198-0.220 s against 0.224-0.236 s with two
+// chunks of half the length (longer still, 167 sweeps: 0.199 s).
+constexpr uint64_t kWordsSweepCostSites = 50000;
+// Chunks of the second stream in flight at once: the next ones are queued
+// while the first runs, so that stream never waits for the host.
+constexpr int kSideChunks = 3;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
