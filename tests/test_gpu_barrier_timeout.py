@@ -3,7 +3,8 @@ barriers, forced from the host: LATTICE_BARRIER_TICKS=0 bounds every wait by
 zero ticks of the device wall clock, so a block that would have to wait
 raises the lattice's error flag and goes on (every kernel still ends).  The
 state is then invalid, and every read of it must say so with LAT_EHIP:
-lattice_observables, lattice_observables_batch and lattice_series_read.  A
+lattice_observables, lattice_observables_batch, lattice_observables_batch_noalloc
+and lattice_series_read.  A
 lattice made afterwards, with the normal bound, is unaffected."""
 import sys
 
@@ -40,6 +41,9 @@ def test_barrier_time_out_is_reported_by_every_read(monkeypatch):
     assert e.value.code == lat.LAT_EHIP
     with pytest.raises(lat.LatticeError) as e:
         lat.BatchObservables(1)([g])
+    assert e.value.code == lat.LAT_EHIP
+    with pytest.raises(lat.LatticeError) as e:
+        lat.observables_batch_noalloc([g])
     assert e.value.code == lat.LAT_EHIP
     g.destroy()
 
