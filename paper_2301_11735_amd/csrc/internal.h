@@ -14,9 +14,12 @@
 
 // How a lattice is swept (chosen at create from L and the encoding):
 //   kPathLds    one block holds the whole lattice in LDS for all the sweeps of
-//               a launch (batch.hip); L <= 512;
-//   kPathWords  one launch per phase, many blocks per lattice, Q lanes per
-//               a-word, schedule computed on the device (words.hip); L % 64 == 0;
+//               a launch (batch.hip); by default L <= 256 when L % 64 == 0,
+//               else L <= 512;
+//   kPathWords  many blocks per lattice, Q lanes per a-word, schedule
+//               computed on the device (words.hip): one persistent launch
+//               per call up to L = 1024, else one launch per phase;
+//               L % 64 == 0, L <= 2048;
 //   kPathPhase  one launch per phase, one thread per a-word (phase.hip).
 // Int8 lattices with L % 64 == 0 on the last two paths are swept on a 2-bit
 // copy in their scratch (packed before the sweeps of a call, unpacked after).
@@ -89,9 +92,8 @@ int enqueue_offchip_sweeps(lattice *const *hs, int32_t count, const uint32_t *sw
 // sweeps[i] (null: `every`) with intervals = 1 and no records, or, with
 // records, an observation series of one lattice: intervals x every sweeps, a
 // kSeriesRecord record after each interval.  *ran = false (nothing
-// enqueued) when the persistent form is off (by default above L = 512, or
-// above L = 1024 for a series; LATTICE_WORDS_PERSISTENT=0|1 overrides) or
-// cannot be launched here; the
+// enqueued) when the persistent form is off (by default above L = 1024;
+// LATTICE_WORDS_PERSISTENT=0|1 overrides) or cannot be launched here; the
 // caller then uses the per-phase launches.  Packed int8 lattices must
 // already be on their 2-bit copy.
 int enqueue_words_persistent(lattice *const *hs, int32_t count, const uint32_t *sweeps, uint32_t intervals,
