@@ -379,6 +379,44 @@ def test_batched_config_invariants():
             assert b.track_nJ == b.bond_ss - a.bond_ss
 
 
+def test_batched_config_graph_in_the_timed_launch_shape(monkeypatch):
+    """The batched workload in the launch configuration bench.py times: all
+    256 lattices in one HIP graph of observation intervals (50 sweeps each)
+    with 512-thread blocks, as the autotuner picks for this shape.  Every
+    16th lattice is compared with the oracle bit for bit (state and every
+    interval's records); every lattice's records hold the exact charge and a
+    tracker equal to the recomputed sums' changes."""
+    monkeypatch.setenv("LATTICE_BATCH_THREADS", "512")
+    _say("case batched config as one graph, 512 threads")
+    specs = workloads.batched_specs()
+    every, intervals = specs[0].every, 3
+    gs = [_make(s) for s in specs]
+    first = lat.BatchObservables(len(gs))(gs)
+    graph = lat.BatchGraph(gs, every, intervals)
+    graph.launch(1)
+    recs = graph.read_array()  # (intervals, lattices)
+    graph.destroy()
+    for i, (s, a) in enumerate(zip(specs, first)):
+        Q, _ = lat.charge_target(s.L, s.n)
+        r = recs[:, i]
+        assert (r["sum_S"] == Q).all(), f"seed {s.seed}"
+        assert (r["track_nD"] == r["n_charged"] - a.n_charged).all(), f"seed {s.seed}"
+        assert (r["track_nV"] == r["bond_SS"] - a.bond_SS).all(), f"seed {s.seed}"
+        assert (r["track_nJ"] == r["bond_ss"] - a.bond_ss).all(), f"seed {s.seed}"
+    for i in range(0, len(specs), 16):
+        s, g = specs[i], gs[i]
+        o = _oracle(s)
+        for k in range(intervals):
+            o.sweeps(every)
+            r = recs[k, i]
+            assert [int(r[f]) for f in ("sum_S", "n_charged", "bond_SS", "bond_ss", "M", "M_stag", "C_stag")] \
+                == o.observables().tolist(), f"seed {s.seed} interval {k}"
+            assert [int(r["track_nD"]), int(r["track_nV"]), int(r["track_nJ"])] == o.track.tolist()
+        assert np.array_equal(g.read_state(), o.codes), f"seed {s.seed}"
+    for g in gs:
+        g.destroy()
+
+
 # ---------------------------------------------------------------- serving
 def test_served_results_equal_alone_and_oracle():
     """Requests served in a mix (continuous batching, small pool so requests
