@@ -214,6 +214,20 @@ def test_word_path_matches_oracle(spec, persistent, block, monkeypatch):
     _run_parity(spec, [1, 3, 10] if spec.L <= 1024 else [1, 2])
 
 
+@pytest.mark.parametrize("lanes", ["1", "8"])
+def test_word_path_per_phase_lane_counts_match_oracle(lanes, monkeypatch):
+    """The per-phase word kernel with 1 and 8 lanes per a-word (the defaults
+    are 4 up to L = 1024 and 2 above; LATTICE_WORDS_PHASE_LANES selects
+    others): bit-exact against the oracle, both encodings, 5 and 9 words per
+    class row."""
+    monkeypatch.setenv("LATTICE_PATH", "words")
+    monkeypatch.setenv("LATTICE_WORDS_PERSISTENT", "0")
+    monkeypatch.setenv("LATTICE_WORDS_PHASE_LANES", lanes)
+    for spec in (SMALL.with_(L=320, encoding=0, seed=1700), SMALL.with_(L=576, encoding=1, T=0.6, seed=1701)):
+        _say(f"case per-phase lanes={lanes} L={spec.L}")
+        _run_parity(spec, [1, 3])
+
+
 @pytest.mark.parametrize("spec", [
     SMALL.with_(L=64, encoding=0, seed=78),
     SMALL.with_(L=4096, encoding=0, T=1.1, seed=79),
