@@ -146,6 +146,35 @@ def test_degenerate_cases(kw):
     _run_parity(spec2, [1, 3, 10])
 
 
+def test_empty_and_zero_work_calls_change_nothing():
+    """Calls with nothing to do, on lattices of the three paths (on-chip
+    L = 64, multi-block word L = 320, phase kernel L = 4096): zero sweeps,
+    an empty batch and a batch given zero sweeps, observables of no lattices
+    (buffered and allocation-free), an observation series of zero intervals.
+    Afterwards each lattice carries on exactly as the oracle does."""
+    specs = [SMALL.with_(L=64, encoding=1, seed=1800), SMALL.with_(L=320, encoding=0, seed=1801),
+             SMALL.with_(L=4096, encoding=1, T=1.1, seed=1802)]
+    gs = [_make(s) for s in specs]
+    os_ = [_oracle(s) for s in specs]
+    _say("case empty and zero-work calls")
+    for g in gs:
+        g.sweep(0)
+        assert g.sweep_series(0, 1) == []
+    lat.sweep_batch([], 5)
+    lat.sweep_batch(gs, 0)
+    assert lat.BatchObservables(4)([]) == []
+    assert lat.observables_batch_noalloc([]) == []
+    for s, g, o in zip(specs, gs, os_):
+        _assert_same(g, o, f"untouched L={s.L}")
+        assert g.observables().sweep == 0
+    lat.sweep_batch(gs, 3)
+    for s, g, o in zip(specs, gs, os_):
+        o.sweeps(3)
+        _assert_same(g, o, f"after 3 sweeps L={s.L}")
+        assert g.observables().sweep == 3
+        g.destroy()
+
+
 def test_mid_config_parity_first_sweeps():
     """MID (L=1024, int8): bit-exact state and observables for the first sweeps."""
     _run_parity(workloads.MID, [1, 2, 3])
